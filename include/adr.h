@@ -1,0 +1,185 @@
+/*
+ * adr.h - C ABI of the MI355X (gfx950) AdR-Gaussian tile rasterizer.
+ *
+ * Forward path of "AdR-Gaussian: Accelerating Gaussian Splatting with
+ * Adaptive Radius" (arXiv 2409.08669): the six-stage tile rasterizer of
+ * Sec. 3.2 with the early culling of Gaussian-tile pairs by adaptive radius
+ * (Sec. 4.2, Eqs. 5-8) or by the axis-aligned bounding box (Sec. 4.3,
+ * Eqs. 9-11), the per-pixel load counters of Eq. 12, the load statistic of
+ * Eq. 13, and a load-balancing render mode that caps the number of Gaussians
+ * a pixel blends.
+ *
+ * Conventions shared by every entry point:
+ *  - All device pointers refer to memory of the current HIP device.
+ *  - Work is enqueued on the caller's stream (a hipStream_t passed as void*;
+ *    NULL = the null stream). adr_render waits once per frame for a 16-byte
+ *    device-to-host copy (the pair count); everything else is asynchronous.
+ *  - Functions return ADR_OK or a negative adr_status; adr_last_error()
+ *    returns a thread-local message for the last failure. No C++ exception
+ *    crosses this boundary.
+ *  - Argument errors (NULL pointers, bad sizes, unsupported modes) are
+ *    detected on the host before anything is enqueued.
+ */
+#ifndef ADR_H
+#define ADR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ADR_OK = 0,
+  ADR_E_INVALID = -1,     /* bad argument; nothing was enqueued */
+  ADR_E_OOM = -2,         /* a device or pinned allocation failed */
+  ADR_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+  ADR_E_UNSUPPORTED = -4, /* valid request this library does not implement */
+  ADR_E_WORKSPACE = -5    /* caller's pair buffers too small; see adr_frame.n_pairs */
+} adr_status;
+
+/* Pair culling of the Preprocess stage. */
+typedef enum {
+  ADR_CULL_3SIGMA = 0,   /* baseline: square of radius r_o = 3 sqrt(lambda'_max) (Sec. 4.2) */
+  ADR_CULL_ADAPTIVE = 1, /* r = min(sqrt(2 lambda'_max ln(sigma/alpha_low)), r_o) (Eqs. 7-8) */
+  ADR_CULL_AABB = 2      /* r_x, r_y = min(sqrt(2 Sigma'_X|Y ln(sigma/alpha_low)), r_o) (Eqs. 10-11) */
+} adr_cull;
+
+/* Opaque scene: the Gaussians of Sec. 3.1 (Eq. 1) in library-owned device
+ * memory, immutable after creation; may be shared by concurrent renders. */
+typedef struct adr_scene adr_scene;
+
+/* Opaque per-stream scratch (per-Gaussian records, pair and sort buffers,
+ * tile ranges). Grows on demand; one workspace must not be used by two
+ * renders at the same time. */
+typedef struct adr_workspace adr_workspace;
+
+/* Scene description (Sec. 3.1): centre, covariance as scale and rotation,
+ * opacity and SH colour. Arrays are row-major float32, one row per Gaussian:
+ *   means          N x 3           world-space centres
+ *   log_scales     N x 3           per-axis log standard deviation
+ *   quats          N x 4           rotation quaternion (w, x, y, z), any norm > 0
+ *   opacity_logits N               opacity = 1 / (1 + exp(-logit))
+ *   sh             N x K x 3       real SH coefficients, K = (sh_degree+1)^2,
+ *                                  index l*l + l + m (Condon-Shortley phase)
+ * The arrays are copied (and transposed to planes) during adr_create_scene;
+ * the caller keeps ownership. pointers_on_device = 1: device pointers; 0: host. */
+typedef struct {
+  int64_t n;
+  int32_t sh_degree; /* 0..3 */
+  int32_t pointers_on_device;
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opacity_logits;
+  const float* sh;
+} adr_scene_desc;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).
+ * p_cam = R p_world + t with world_to_cam = [R | t] row-major 3 x 4.
+ * Pixel (i, j) covers [i, i+1) x [j, j+1) in image coordinates u = fx x/z + cx.
+ * Gaussians with camera-space z <= near_z are not drawn. */
+typedef struct {
+  double world_to_cam[12];
+  double fx, fy, cx, cy;
+  int32_t width, height; /* 1 .. 65535 each */
+  double near_z;
+} adr_camera;
+
+/* Flags of adr_render_params.flags */
+#define ADR_FLAG_TIMING 1u      /* record per-stage HIP events; see adr_workspace_stage_times */
+#define ADR_FLAG_NO_EXACT_BAND 2u /* skip the FP64 re-decision of near-threshold alphas and
+                                     transmittances (faster, no longer bit-matched to FP64) */
+
+typedef struct {
+  int32_t cull;      /* adr_cull */
+  int32_t lb_cap;    /* load-balancing mode: a pixel stops after blending this many Gaussians; 0 = off */
+  double alpha_low;  /* minimum splatting opacity, 1/255 (Sec. 5.1.2); cull and skip threshold */
+  double alpha_max;  /* upper clamp of alpha, 0.99 */
+  double t_min;      /* a pixel stops once its transmittance falls below this, 1e-4 */
+  double lowpass;    /* added to the diagonal of Sigma', 0.3 */
+  double ewa_clamp;  /* EWA Jacobian evaluated at x/z clamped to +- ewa_clamp * (W/2)/fx, 1.3 */
+  float background[3];
+  uint32_t flags;    /* ADR_FLAG_* */
+} adr_render_params;
+
+/* Outputs of one frame. Every pointer is caller-owned device memory; all but
+ * image may be NULL to skip that output.
+ *   image         3 x H x W float32, C + T * background (Eq. 3)
+ *   final_t       H x W     float32, transmittance when the pixel stopped
+ *   l_iter        H x W     uint32, entries of the tile list examined (the thread's work)
+ *   l_blend       H x W     uint32, Gaussians blended (Eq. 12)
+ *   load_sums     4         uint64: sum l_blend, sum l_blend^2, sum l_iter, sum l_iter^2
+ *                           over H x W (Eq. 13 follows exactly on the host)
+ *   tiles_touched N         uint32 per Gaussian (Preprocess)
+ *   keys, values  pair_capacity   sorted (tile << 32 | depth bits) keys and Gaussian ids
+ *   ranges        2 x T     uint32 [first, last+1) per tile, (0, 0) when empty,
+ *                           T = ceil(W/16) * ceil(H/16), tile id = ty * ceil(W/16) + tx
+ * n_pairs is written on return (host) with the frame's Gaussian-tile pair count.
+ * If keys/values are given and n_pairs > pair_capacity, adr_render returns
+ * ADR_E_WORKSPACE after writing the image (the pair lists are not copied). */
+typedef struct {
+  float* image;
+  float* final_t;
+  uint32_t* l_iter;
+  uint32_t* l_blend;
+  uint64_t* load_sums;
+  uint32_t* tiles_touched;
+  uint64_t* keys;
+  uint32_t* values;
+  uint32_t* ranges;
+  int64_t pair_capacity;
+  int64_t n_pairs;
+} adr_frame;
+
+/* Per-Gaussian gradients, same shapes as adr_scene_desc arrays (device). */
+typedef struct {
+  float* d_means;
+  float* d_log_scales;
+  float* d_quats;
+  float* d_opacity_logits;
+  float* d_sh;
+} adr_scene_grads;
+
+/* Creates a scene from desc (see adr_scene_desc). Returns ADR_E_INVALID for
+ * n < 0, sh_degree outside 0..3 or NULL arrays with n > 0; ADR_E_OOM when the
+ * device copy cannot be allocated. Synchronous. */
+adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** out);
+void adr_destroy_scene(adr_scene* scene);
+int64_t adr_scene_size(const adr_scene* scene);
+int64_t adr_scene_bytes(const adr_scene* scene);
+
+adr_status adr_workspace_create(adr_workspace** out);
+void adr_workspace_destroy(adr_workspace* ws);
+
+/* Renders one frame: Preprocess (projection, SH colour, cull per params.cull),
+ * InclusiveSum, DuplicateWithKeys, SortPairs, IdentifyTileRanges and Render
+ * (Sec. 3.2), all on the given stream. Outputs are written into out. */
+adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
+                      adr_frame* out, adr_workspace* ws, void* stream);
+
+/* Gradient of a scalar loss with respect to the scene, given dL/dimage.
+ * Not implemented in this version: returns ADR_E_UNSUPPORTED. */
+adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
+                               const adr_frame* fwd, const float* dl_dimage, adr_scene_grads* grads,
+                               adr_workspace* ws, void* stream);
+
+/* Stage durations (ms) of the last adr_render on ws that had ADR_FLAG_TIMING:
+ * [0] preprocess, [1] inclusive sum, [2] host wait for the pair count,
+ * [3] duplicate with keys, [4] sort, [5] tile ranges, [6] render.
+ * Waits for the frame to finish. Returns the number of stages written. */
+int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
+
+/* Per-frame counters of the last adr_render on ws (host values; the frame
+ * must have finished): [0] pairs, [1] visible Gaussians (tiles_touched > 0),
+ * [2] exact-band alpha re-decisions, [3] exact-band transmittance replays. */
+int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n);
+
+const char* adr_last_error(void);
+const char* adr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADR_H */

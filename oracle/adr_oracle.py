@@ -203,6 +203,10 @@ def preprocess(scene, cam, params: Params) -> dict:
     c = cov2[:, 1, 1] + params.lowpass
 
     det = a * c - b * b
+    # Reading: a degenerate projected covariance (det <= 0, possible only with
+    # lowpass = 0) is not drawn.
+    valid = valid & (det > 0)
+    det = np.where(det > 0, det, 1.0)
     conic = np.stack([c / det, -b / det, a / det], axis=1)
     # Larger eigenvalue of Sigma' (the paper defers its formula to supplementary
     # material). mid + sqrt(mid^2 - det) equals mid + sqrt(((a - c)/2)^2 + b^2);

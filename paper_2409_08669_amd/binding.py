@@ -1,0 +1,325 @@
+"""ctypes binding of ``libadr.so`` (include/adr.h), names as in the C ABI.
+
+Argument marshalling only: every stage of a frame runs in the HIP library.
+PyTorch supplies device memory and the current stream. Importing this module
+does not touch the GPU; loading the library fails loudly if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import pathlib
+
+import numpy as np
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libadr.so"
+_lib = None
+
+ADR_OK = 0
+ADR_E_INVALID = -1
+ADR_E_OOM = -2
+ADR_E_HIP = -3
+ADR_E_UNSUPPORTED = -4
+ADR_E_WORKSPACE = -5
+
+ADR_CULL_3SIGMA = 0
+ADR_CULL_ADAPTIVE = 1
+ADR_CULL_AABB = 2
+
+ADR_FLAG_TIMING = 1
+ADR_FLAG_NO_EXACT_BAND = 2
+
+STAGES = ("preprocess", "inclusive_sum", "host_wait", "duplicate", "sort", "ranges", "render")
+
+EXPORTS = (
+    "adr_create_scene", "adr_destroy_scene", "adr_scene_size", "adr_scene_bytes",
+    "adr_workspace_create", "adr_workspace_destroy", "adr_render", "adr_render_backward",
+    "adr_workspace_stage_times", "adr_workspace_counters", "adr_last_error", "adr_version",
+)
+
+
+class AdrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"adr status {status}: {msg}")
+        self.status = status
+
+
+class adr_scene_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("pointers_on_device", ctypes.c_int32),
+                ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
+                ("opacity_logits", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class adr_camera(ctypes.Structure):
+    _fields_ = [("world_to_cam", ctypes.c_double * 12), ("fx", ctypes.c_double), ("fy", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("near_z", ctypes.c_double)]
+
+
+class adr_render_params(ctypes.Structure):
+    _fields_ = [("cull", ctypes.c_int32), ("lb_cap", ctypes.c_int32), ("alpha_low", ctypes.c_double),
+                ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double), ("lowpass", ctypes.c_double),
+                ("ewa_clamp", ctypes.c_double), ("background", ctypes.c_float * 3), ("flags", ctypes.c_uint32)]
+
+
+class adr_frame(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("final_t", ctypes.c_void_p), ("l_iter", ctypes.c_void_p),
+                ("l_blend", ctypes.c_void_p), ("load_sums", ctypes.c_void_p), ("tiles_touched", ctypes.c_void_p),
+                ("keys", ctypes.c_void_p), ("values", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
+                ("pair_capacity", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
+
+
+def lib_path() -> pathlib.Path:
+    return _LIB_PATH
+
+
+def load(path=None):
+    """Loads the HIP library once; raises if it is missing (no CPU fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = pathlib.Path(path) if path else _LIB_PATH
+    if not p.exists():
+        raise ImportError(f"{p} is not built; run `python -m paper_2409_08669_amd.build` (needs hipcc)")
+    lib = ctypes.CDLL(str(p))
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.adr_create_scene.argtypes = [ctypes.POINTER(adr_scene_desc), ctypes.POINTER(vp)]
+    lib.adr_create_scene.restype = i32
+    lib.adr_destroy_scene.argtypes = [vp]
+    lib.adr_destroy_scene.restype = None
+    lib.adr_scene_size.argtypes = [vp]
+    lib.adr_scene_size.restype = i64
+    lib.adr_scene_bytes.argtypes = [vp]
+    lib.adr_scene_bytes.restype = i64
+    lib.adr_workspace_create.argtypes = [ctypes.POINTER(vp)]
+    lib.adr_workspace_create.restype = i32
+    lib.adr_workspace_destroy.argtypes = [vp]
+    lib.adr_workspace_destroy.restype = None
+    lib.adr_render.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
+                               ctypes.POINTER(adr_frame), vp, vp]
+    lib.adr_render.restype = i32
+    lib.adr_render_backward.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
+                                        ctypes.POINTER(adr_frame), vp, vp, vp, vp]
+    lib.adr_render_backward.restype = i32
+    lib.adr_workspace_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    lib.adr_workspace_stage_times.restype = i32
+    lib.adr_workspace_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
+    lib.adr_workspace_counters.restype = i32
+    lib.adr_last_error.argtypes = []
+    lib.adr_last_error.restype = ctypes.c_char_p
+    lib.adr_version.argtypes = []
+    lib.adr_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().adr_last_error().decode()
+
+
+def _check(status: int):
+    if status != ADR_OK:
+        raise AdrError(status, last_error())
+
+
+@dataclasses.dataclass
+class RenderParams:
+    cull: int = ADR_CULL_AABB
+    lb_cap: int = 0
+    alpha_low: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    lowpass: float = 0.3
+    ewa_clamp: float = 1.3
+    background: tuple = (0.0, 0.0, 0.0)
+    flags: int = 0
+
+    def to_c(self) -> adr_render_params:
+        p = adr_render_params()
+        p.cull, p.lb_cap = int(self.cull), int(self.lb_cap)
+        p.alpha_low, p.alpha_max, p.t_min = float(self.alpha_low), float(self.alpha_max), float(self.t_min)
+        p.lowpass, p.ewa_clamp = float(self.lowpass), float(self.ewa_clamp)
+        for i in range(3):
+            p.background[i] = float(self.background[i])
+        p.flags = int(self.flags)
+        return p
+
+
+def camera_to_c(cam) -> adr_camera:
+    """Any object with world_to_cam (3x4), fx, fy, cx, cy, width, height, near."""
+    c = adr_camera()
+    w2c = np.asarray(cam.world_to_cam, dtype=np.float64).reshape(12)
+    for i in range(12):
+        c.world_to_cam[i] = float(w2c[i])
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.near_z = float(getattr(cam, "near", 0.2))
+    return c
+
+
+class Scene:
+    """Device copy of a Gaussian scene (adr_create_scene). Accepts numpy arrays
+    (host) or torch tensors on the GPU; float32, row-major."""
+
+    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree: int):
+        lib = load()
+        arrays = [means, log_scales, quats, opacity_logits, sh]
+        on_device = hasattr(means, "is_cuda") and bool(means.is_cuda)
+        keep = []
+        ptrs = []
+        for a in arrays:
+            if on_device:
+                a = a.contiguous().float()
+                keep.append(a)
+                ptrs.append(a.data_ptr())
+            else:
+                a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+                keep.append(a)
+                ptrs.append(a.ctypes.data)
+        d = adr_scene_desc()
+        d.n = int(keep[0].shape[0])
+        d.sh_degree = int(sh_degree)
+        d.pointers_on_device = 1 if on_device else 0
+        d.means, d.log_scales, d.quats, d.opacity_logits, d.sh = ptrs
+        h = ctypes.c_void_p()
+        _check(lib.adr_create_scene(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.n = d.n
+        self.sh_degree = int(sh_degree)
+
+    @classmethod
+    def from_synth(cls, s) -> "Scene":
+        return cls(s.means, s.log_scales, s.quats, s.opacity_logits, s.sh, s.sh_degree)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def bytes(self) -> int:
+        return int(load().adr_scene_bytes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().adr_destroy_scene(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Workspace:
+    """adr_workspace: per-stream scratch that grows on demand."""
+
+    def __init__(self):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.adr_workspace_create(ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stage_times(self) -> dict:
+        buf = (ctypes.c_float * len(STAGES))()
+        k = load().adr_workspace_stage_times(self._h, buf, len(STAGES))
+        return {STAGES[i]: float(buf[i]) for i in range(k)}
+
+    def counters(self) -> dict:
+        buf = (ctypes.c_int64 * 5)()
+        k = load().adr_workspace_counters(self._h, buf, 5)
+        names = ("pairs", "visible", "band_redecisions", "t_replays", "sort_spin_limit")
+        return {names[i]: int(buf[i]) for i in range(k)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().adr_workspace_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    return 0 if t is None else int(t.data_ptr())
+
+
+def render(scene: Scene, cam, params: RenderParams, ws: Workspace, image, final_t=None, l_iter=None,
+           l_blend=None, load_sums=None, tiles_touched=None, keys=None, values=None, ranges=None,
+           pair_capacity: int = 0, stream=None) -> int:
+    """adr_render into caller-allocated device tensors; returns the pair count.
+    Raises AdrError on any non-OK status (ADR_E_WORKSPACE carries n_pairs)."""
+    import torch
+
+    lib = load()
+    f = adr_frame()
+    f.image, f.final_t, f.l_iter, f.l_blend = _ptr(image), _ptr(final_t), _ptr(l_iter), _ptr(l_blend)
+    f.load_sums, f.tiles_touched = _ptr(load_sums), _ptr(tiles_touched)
+    f.keys, f.values, f.ranges = _ptr(keys), _ptr(values), _ptr(ranges)
+    f.pair_capacity = int(pair_capacity)
+    c = camera_to_c(cam)
+    p = params.to_c()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = lib.adr_render(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f), ws.handle,
+                        ctypes.c_void_p(int(stream)))
+    if st == ADR_E_WORKSPACE:
+        e = AdrError(st, last_error())
+        e.n_pairs = int(f.n_pairs)
+        raise e
+    _check(st)
+    return int(f.n_pairs)
+
+
+def render_frame(scene: Scene, cam, params: RenderParams, ws: Workspace = None, debug: bool = False,
+                 device: str = "cuda") -> dict:
+    """Allocates the outputs with torch and renders one frame. With debug=True
+    the per-Gaussian counts, sorted pairs and tile ranges are returned too
+    (a first call sizes the pair buffers)."""
+    import torch
+
+    ws = ws or Workspace()
+    w, h = int(cam.width), int(cam.height)
+    tiles = ((w + 15) // 16) * ((h + 15) // 16)
+    out = dict(
+        image=torch.empty((3, h, w), dtype=torch.float32, device=device),
+        final_t=torch.empty((h, w), dtype=torch.float32, device=device),
+        l_iter=torch.empty((h, w), dtype=torch.int32, device=device),
+        l_blend=torch.empty((h, w), dtype=torch.int32, device=device),
+        load_sums=torch.zeros(4, dtype=torch.int64, device=device),
+    )
+    extra = {}
+    cap = 0
+    if debug:
+        extra = dict(tiles_touched=torch.empty(max(scene.n, 1), dtype=torch.int32, device=device),
+                     ranges=torch.empty((tiles, 2), dtype=torch.int32, device=device))
+        n_pairs = render(scene, cam, params, ws, **out, **extra)
+        cap = max(n_pairs, 1)
+        extra["keys"] = torch.empty(cap, dtype=torch.int64, device=device)
+        extra["values"] = torch.empty(cap, dtype=torch.int32, device=device)
+    n_pairs = render(scene, cam, params, ws, **out, **extra, pair_capacity=cap)
+    out.update(extra)
+    out["n_pairs"] = n_pairs
+    if debug:
+        out["keys"] = out["keys"][:n_pairs]
+        out["values"] = out["values"][:n_pairs]
+        out["tiles_touched"] = out["tiles_touched"][:scene.n]
+    out["workspace"] = ws
+    return out
+
+
+def load_stats_from_sums(sums, n_pixels: int):
+    """Exact (mean, population std) from the integer sums (sum, sum of squares)
+    that adr_render writes; Eq. 13 over all H x W pixels."""
+    import math
+    s1, s2 = int(sums[0]), int(sums[1])
+    mean = s1 / n_pixels
+    var = (n_pixels * s2 - s1 * s1) / (n_pixels * n_pixels)
+    return mean, math.sqrt(max(var, 0.0))

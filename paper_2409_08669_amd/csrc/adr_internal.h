@@ -1,0 +1,162 @@
+// Internal declarations of the gfx950 rasterizer library: device layouts,
+// launch helpers and the host-side objects behind the opaque C handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/adr.h"
+
+namespace adr {
+
+constexpr int kTile = 16;     // 16 x 16 pixel tiles (Sec. 3.2)
+constexpr int kQuad = 8;      // each wave of a tile's workgroup owns an 8 x 8 quadrant
+constexpr int kWave = 64;     // CDNA wavefront
+
+// ---------------------------------------------------------------------------
+// Scene in device memory (structure of arrays, coalesced per Gaussian index)
+// ---------------------------------------------------------------------------
+struct DeviceScene {
+  int64_t n = 0;
+  int32_t sh_degree = 0;
+  int32_t n_coeff = 1;       // (degree+1)^2
+  float4* geo_a = nullptr;   // (mean.x, mean.y, mean.z, opacity logit)
+  float4* geo_b = nullptr;   // (log_scale.x, .y, .z, 0)
+  float4* geo_q = nullptr;   // quaternion (w, x, y, z), as given
+  float* sh = nullptr;       // planes [3*K][n]: plane (k*3 + channel)
+  size_t bytes = 0;
+};
+
+// ---------------------------------------------------------------------------
+// Per-Gaussian outputs of Preprocess
+// ---------------------------------------------------------------------------
+// Render record, 64 bytes, read by the blend kernel through the sorted ids.
+// The splatting opacity in the log2 domain is
+//   q(dx, dy) = qa dx^2 + qb dx dy + qc dy^2 + ql,   alpha = min(alpha_max, 2^q)
+// with (qa, qb, qc) = -(1/2) log2(e) (conic_a, 2 conic_b, conic_c) and
+// ql = log2(opacity); dx = x - i, dy = y - j for pixel (i, j).
+struct alignas(16) RenderRecord {
+  double x, y;            // projected centre, pixel centres at integers
+  float qa, qb, qc, ql;
+  float r, g, b;
+  uint32_t box_x;         // lo | hi << 16: pixel columns the alpha_low ellipse can reach
+  uint32_t box_y;         // lo | hi << 16: pixel rows (lo > hi: none)
+  uint32_t pad[3];
+};
+static_assert(sizeof(RenderRecord) == 64, "render record is four 16-byte loads");
+
+// FP64 values for exact decisions near alpha_low and t_min.
+struct alignas(16) ExactRecord {
+  double ca, cb, cc;      // conic = Sigma'^-1 (a, b, c)
+  double opacity;
+};
+
+// ---------------------------------------------------------------------------
+// Camera and parameters as kernel arguments
+// ---------------------------------------------------------------------------
+struct CamArgs {
+  double r[9];
+  double t[3];
+  double cam_pos[3];
+  double fx, fy, cx, cy;
+  double near_z;
+  double lim_x, lim_y;      // EWA clamp of x/z and y/z
+  int32_t width, height;
+  int32_t tiles_x, tiles_y;
+};
+
+struct CullArgs {
+  int32_t mode;
+  double alpha_low;
+  double lowpass;
+};
+
+struct BlendArgs {
+  float alpha_max;
+  float t_min;
+  float q_low;              // log2(alpha_low) rounded to float
+  float q_band;             // half-width of the FP64 re-decision band on q
+  float t_band_lo, t_band_hi; // fp32 transmittances that trigger an FP64 replay
+  double alpha_low_d, alpha_max_d, t_min_d;
+  float bg[3];
+  int32_t lb_cap;
+  int32_t exact;
+};
+
+// ---------------------------------------------------------------------------
+// Host objects behind the opaque handles
+// ---------------------------------------------------------------------------
+struct SortBuffers {
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint32_t* block_hist = nullptr; // look-back status words, tile counters, digit histograms
+  unsigned long long* err = nullptr; // look-back spin-limit hits (never expected)
+  int64_t capacity = 0;
+  int64_t hist_capacity = 0;
+};
+
+}  // namespace adr
+
+struct adr_scene {
+  adr::DeviceScene d;
+};
+
+struct adr_workspace {
+  int64_t gauss_capacity = 0;
+  adr::RenderRecord* rec = nullptr;
+  adr::ExactRecord* exact = nullptr;
+  uint2* tile_rect = nullptr;      // (tx_lo | tx_hi << 16, ty_lo | ty_hi << 16)
+  float* depth = nullptr;
+  uint32_t* touched = nullptr;
+  uint32_t* offsets = nullptr;     // inclusive sum of touched
+  uint32_t* scan_partials = nullptr;
+  int64_t scan_partials_capacity = 0;
+  adr::SortBuffers sort;
+  uint32_t* ranges = nullptr;      // 2 * tiles
+  int64_t ranges_capacity = 0;
+  unsigned long long* dev_counters = nullptr; // [0] pairs, [1] visible, [2] band, [3] replays, [4] sort spin limit
+  unsigned long long* host_counters = nullptr; // pinned mirror
+  hipEvent_t ev[8] = {};
+  bool timing_valid = false;
+  hipStream_t last_stream = nullptr;
+  int64_t last_pairs = 0;
+};
+
+namespace adr {
+
+// Thread-local error message for adr_last_error.
+void set_error(const std::string& msg);
+adr_status hip_fail(hipError_t e, const char* what);
+
+#define ADR_HIP(call)                                          \
+  do {                                                         \
+    hipError_t _e = (call);                                    \
+    if (_e != hipSuccess) return ::adr::hip_fail(_e, #call);   \
+  } while (0)
+
+// Launchers (each enqueues on `stream`, returns hipSuccess or the error).
+hipError_t launch_pack_scene(const adr_scene_desc& desc, const float* means, const float* log_scales,
+                             const float* quats, const float* logits, const float* sh, DeviceScene& d,
+                             hipStream_t stream);
+hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
+                             hipStream_t stream);
+hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
+                                hipStream_t stream);
+int64_t inclusive_sum_partials(int64_t n);
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* touched, const uint2* tile_rect,
+                            const float* depth, int64_t n, int64_t n_pairs, int32_t tiles_x, uint64_t* keys,
+                            uint32_t* vals, hipStream_t stream);
+hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* result_buffer,
+                             hipStream_t stream);
+int64_t sort_hist_entries(int64_t n_pairs);
+hipError_t launch_tile_ranges(const uint64_t* keys, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
+                              hipStream_t stream);
+hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
+                         const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
+                         const BlendArgs& blend, adr_frame* out, unsigned long long* counters, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
+
+}  // namespace adr

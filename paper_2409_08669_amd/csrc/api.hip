@@ -1,0 +1,344 @@
+// C ABI: workspace management and the per-frame orchestration of the six
+// stages of Sec. 3.2 on the caller's stream.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "adr_internal.h"
+
+namespace adr {
+
+namespace {
+thread_local std::string g_error;
+constexpr int kCounters = 8;
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+adr_status hip_fail(hipError_t e, const char* what) {
+  g_error = std::string(what) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();
+  return ADR_E_HIP;
+}
+
+namespace {
+
+template <typename T>
+adr_status grow(T*& p, int64_t& cap, int64_t need, const char* what) {
+  if (need <= cap && p) return ADR_OK;
+  int64_t n = need < 1 ? 1 : need;
+  n = n + n / 4;  // headroom so that frame-to-frame jitter does not reallocate
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+  if (hipMalloc(&p, (size_t)n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error(std::string("workspace allocation failed: ") + what);
+    return ADR_E_OOM;
+  }
+  cap = n;
+  return ADR_OK;
+}
+
+adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
+  if (n <= ws->gauss_capacity && ws->rec) return ADR_OK;
+  int64_t cap = ws->gauss_capacity;
+  int64_t c1 = cap, c2 = cap, c3 = cap, c4 = cap, c5 = cap, c6 = cap;
+  adr_status st;
+  if ((st = grow(ws->rec, c1, n, "records")) != ADR_OK) return st;
+  if ((st = grow(ws->exact, c2, n, "exact records")) != ADR_OK) return st;
+  if ((st = grow(ws->tile_rect, c3, n, "tile rects")) != ADR_OK) return st;
+  if ((st = grow(ws->depth, c4, n, "depths")) != ADR_OK) return st;
+  if ((st = grow(ws->touched, c5, n, "tiles_touched")) != ADR_OK) return st;
+  if ((st = grow(ws->offsets, c6, n, "offsets")) != ADR_OK) return st;
+  int64_t m = c1;
+  m = c2 < m ? c2 : m;
+  m = c3 < m ? c3 : m;
+  m = c4 < m ? c4 : m;
+  m = c5 < m ? c5 : m;
+  m = c6 < m ? c6 : m;
+  ws->gauss_capacity = m;
+  return grow(ws->scan_partials, ws->scan_partials_capacity, inclusive_sum_partials(n) + 1, "scan partials");
+}
+
+adr_status ensure_pairs(adr_workspace* ws, int64_t p) {
+  SortBuffers& sb = ws->sort;
+  if (p > sb.capacity || !sb.keys[0]) {
+    int64_t c0 = sb.capacity, c1 = sb.capacity, c2 = sb.capacity, c3 = sb.capacity;
+    adr_status st;
+    if ((st = grow(sb.keys[0], c0, p, "keys")) != ADR_OK) return st;
+    if ((st = grow(sb.keys[1], c1, p, "keys")) != ADR_OK) return st;
+    if ((st = grow(sb.vals[0], c2, p, "values")) != ADR_OK) return st;
+    if ((st = grow(sb.vals[1], c3, p, "values")) != ADR_OK) return st;
+    sb.capacity = c0 < c1 ? c0 : c1;
+    sb.capacity = c2 < sb.capacity ? c2 : sb.capacity;
+    sb.capacity = c3 < sb.capacity ? c3 : sb.capacity;
+  }
+  return grow(sb.block_hist, sb.hist_capacity, sort_hist_entries(p < 1 ? 1 : p), "sort status");
+}
+
+int bits_for(int64_t v) {
+  int b = 0;
+  while (((int64_t)1 << b) < v) ++b;
+  return b;
+}
+
+}  // namespace
+}  // namespace adr
+
+using namespace adr;
+
+extern "C" const char* adr_last_error(void) { return g_error.c_str(); }
+
+extern "C" const char* adr_version(void) { return "adr-gfx950 0.1"; }
+
+extern "C" adr_status adr_workspace_create(adr_workspace** out) {
+  if (!out) {
+    set_error("adr_workspace_create: NULL argument");
+    return ADR_E_INVALID;
+  }
+  *out = nullptr;
+  adr_workspace* ws = new (std::nothrow) adr_workspace();
+  if (!ws) {
+    set_error("adr_workspace_create: host allocation failed");
+    return ADR_E_OOM;
+  }
+  if (hipMalloc(&ws->dev_counters, kCounters * sizeof(unsigned long long)) != hipSuccess ||
+      hipHostMalloc(&ws->host_counters, kCounters * sizeof(unsigned long long), hipHostMallocDefault) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    if (ws->dev_counters) (void)hipFree(ws->dev_counters);
+    delete ws;
+    set_error("adr_workspace_create: allocation failed");
+    return ADR_E_OOM;
+  }
+  std::memset(ws->host_counters, 0, kCounters * sizeof(unsigned long long));
+  ws->sort.err = ws->dev_counters + 4;
+  for (int i = 0; i < 8; ++i) {
+    if (hipEventCreate(&ws->ev[i]) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("adr_workspace_create: hipEventCreate failed");
+      for (int k = 0; k < i; ++k) (void)hipEventDestroy(ws->ev[k]);
+      (void)hipFree(ws->dev_counters);
+      (void)hipHostFree(ws->host_counters);
+      delete ws;
+      return ADR_E_HIP;
+    }
+  }
+  *out = ws;
+  return ADR_OK;
+}
+
+extern "C" void adr_workspace_destroy(adr_workspace* ws) {
+  if (!ws) return;
+  (void)hipDeviceSynchronize();
+  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->depth, ws->touched, ws->offsets, ws->scan_partials,
+                  ws->sort.keys[0], ws->sort.keys[1], ws->sort.vals[0], ws->sort.vals[1], ws->sort.block_hist,
+                  ws->ranges, ws->dev_counters};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (ws->host_counters) (void)hipHostFree(ws->host_counters);
+  for (auto& e : ws->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ws;
+}
+
+static adr_status validate(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                           const adr_frame* out, const adr_workspace* ws) {
+  if (!scene || !cam || !p || !out || !ws) {
+    set_error("adr_render: NULL argument");
+    return ADR_E_INVALID;
+  }
+  if (!out->image) {
+    set_error("adr_render: frame.image is required");
+    return ADR_E_INVALID;
+  }
+  if (cam->width < 1 || cam->height < 1 || cam->width > 65535 || cam->height > 65535) {
+    set_error("adr_render: width and height must be in 1..65535");
+    return ADR_E_INVALID;
+  }
+  if (!(cam->fx > 0) || !(cam->fy > 0) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy) ||
+      !(cam->near_z >= 0)) {
+    set_error("adr_render: fx, fy must be > 0, cx, cy finite and near_z >= 0");
+    return ADR_E_INVALID;
+  }
+  for (double v : cam->world_to_cam)
+    if (!std::isfinite(v)) {
+      set_error("adr_render: world_to_cam must be finite");
+      return ADR_E_INVALID;
+    }
+  if (p->cull < ADR_CULL_3SIGMA || p->cull > ADR_CULL_AABB) {
+    set_error("adr_render: unknown cull mode");
+    return ADR_E_INVALID;
+  }
+  if (!(p->alpha_low > 0 && p->alpha_low < 1) || !(p->alpha_max > 0 && p->alpha_max < 1) ||
+      !(p->alpha_low <= p->alpha_max) || !(p->t_min > 0 && p->t_min < 1) || !(p->lowpass >= 0) ||
+      !(p->ewa_clamp > 0) || p->lb_cap < 0) {
+    set_error("adr_render: parameter out of range (0<alpha_low<=alpha_max<1, 0<t_min<1, lowpass>=0, "
+              "ewa_clamp>0, lb_cap>=0)");
+    return ADR_E_INVALID;
+  }
+  if ((out->keys || out->values) && out->pair_capacity < 0) {
+    set_error("adr_render: negative pair_capacity");
+    return ADR_E_INVALID;
+  }
+  return ADR_OK;
+}
+
+extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                 adr_frame* out, adr_workspace* ws, void* stream_ptr) {
+  adr_status st = validate(scene, cam, p, out, ws);
+  if (st != ADR_OK) return st;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  const DeviceScene& s = scene->d;
+  const int W = cam->width, H = cam->height;
+
+  CamArgs ca{};
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) ca.r[3 * i + j] = cam->world_to_cam[4 * i + j];
+    ca.t[i] = cam->world_to_cam[4 * i + 3];
+  }
+  for (int j = 0; j < 3; ++j)  // camera centre -R^T t
+    ca.cam_pos[j] = -(ca.r[j] * ca.t[0] + ca.r[3 + j] * ca.t[1] + ca.r[6 + j] * ca.t[2]);
+  ca.fx = cam->fx;
+  ca.fy = cam->fy;
+  ca.cx = cam->cx;
+  ca.cy = cam->cy;
+  ca.near_z = cam->near_z;
+  ca.lim_x = p->ewa_clamp * (W / 2.0) / cam->fx;
+  ca.lim_y = p->ewa_clamp * (H / 2.0) / cam->fy;
+  ca.width = W;
+  ca.height = H;
+  ca.tiles_x = (W + kTile - 1) / kTile;
+  ca.tiles_y = (H + kTile - 1) / kTile;
+  const int64_t n_tiles = (int64_t)ca.tiles_x * ca.tiles_y;
+
+  CullArgs cu{};
+  cu.mode = p->cull;
+  cu.alpha_low = p->alpha_low;
+  cu.lowpass = p->lowpass;
+
+  BlendArgs bl{};
+  bl.alpha_max = (float)p->alpha_max;
+  bl.t_min = (float)p->t_min;
+  bl.q_low = (float)std::log2(p->alpha_low);
+  bl.q_band = 1.0f / 4096.0f;  // FP32 q carries ~1e-5 error; the band is >20x that
+  bl.t_band_lo = (float)(p->t_min * (1.0 - 1.0 / 256.0));
+  bl.t_band_hi = (float)(p->t_min * (1.0 + 1.0 / 256.0));
+  bl.alpha_low_d = p->alpha_low;
+  bl.alpha_max_d = p->alpha_max;
+  bl.t_min_d = p->t_min;
+  for (int c = 0; c < 3; ++c) bl.bg[c] = p->background[c];
+  bl.lb_cap = p->lb_cap;
+  bl.exact = (p->flags & ADR_FLAG_NO_EXACT_BAND) ? 0 : 1;
+
+  if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
+  if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;
+  const bool timing = (p->flags & ADR_FLAG_TIMING) != 0;
+  ws->timing_valid = false;
+  ws->last_stream = stream;
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[0], stream));
+
+  // Stage 1: Preprocess (+ pair total and visible count)
+  ADR_HIP(launch_fill_u64(ws->dev_counters, 0ull, kCounters, stream));
+  ADR_HIP(launch_preprocess(s, ca, cu, ws, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
+  // Stage 2: InclusiveSum
+  ADR_HIP(launch_inclusive_sum(ws->touched, ws->offsets, s.n, ws->scan_partials, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[2], stream));
+  // The pair count sizes everything after this point: one 16-byte readback.
+  ADR_HIP(hipMemcpyAsync(ws->host_counters, ws->dev_counters, 2 * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, stream));
+  ADR_HIP(hipStreamSynchronize(stream));
+  const unsigned long long n_pairs_u = ws->host_counters[0];
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
+  if (n_pairs_u >= (1ull << 30)) {
+    set_error("adr_render: more than 2^30 Gaussian-tile pairs in one frame");
+    out->n_pairs = (int64_t)n_pairs_u;
+    return ADR_E_UNSUPPORTED;
+  }
+  const int64_t n_pairs = (int64_t)n_pairs_u;
+  out->n_pairs = n_pairs;
+  ws->last_pairs = n_pairs;
+  if ((st = ensure_pairs(ws, n_pairs)) != ADR_OK) return st;
+
+  // Stage 3: DuplicateWithKeys
+  ADR_HIP(launch_duplicate(ws->offsets, ws->touched, ws->tile_rect, ws->depth, s.n, n_pairs, ca.tiles_x,
+                           ws->sort.keys[0], ws->sort.vals[0], stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[4], stream));
+  // Stage 4: SortPairs over 32 depth bits + tile-id bits
+  int sorted = 0;
+  const int n_bits = 32 + bits_for(n_tiles);
+  ADR_HIP(launch_sort_pairs(ws->sort, n_pairs, n_bits, &sorted, stream));
+  const uint64_t* keys = ws->sort.keys[sorted];
+  const uint32_t* vals = ws->sort.vals[sorted];
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[5], stream));
+  // Stage 5: IdentifyTileRanges
+  ADR_HIP(launch_tile_ranges(keys, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
+  // Stage 6: Render
+  if (out->load_sums) ADR_HIP(launch_fill_u64((unsigned long long*)out->load_sums, 0ull, 4, stream));
+  ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, n_pairs, s.n, ca, bl, out, ws->dev_counters, stream));
+  if (timing) {
+    ADR_HIP(hipEventRecord(ws->ev[7], stream));
+    ws->timing_valid = true;
+  }
+
+  // Optional intermediate outputs.
+  if (out->tiles_touched && s.n > 0)
+    ADR_HIP(hipMemcpyAsync(out->tiles_touched, ws->touched, (size_t)s.n * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, stream));
+  if (out->ranges)
+    ADR_HIP(hipMemcpyAsync(out->ranges, ws->ranges, (size_t)n_tiles * 2 * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, stream));
+  if (out->keys || out->values) {
+    if (n_pairs > out->pair_capacity) {
+      set_error("adr_render: pair_capacity smaller than the frame's pair count (see n_pairs)");
+      return ADR_E_WORKSPACE;
+    }
+    if (out->keys && n_pairs > 0)
+      ADR_HIP(hipMemcpyAsync(out->keys, keys, (size_t)n_pairs * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream));
+    if (out->values && n_pairs > 0)
+      ADR_HIP(hipMemcpyAsync(out->values, vals, (size_t)n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                             stream));
+  }
+  return ADR_OK;
+}
+
+extern "C" adr_status adr_render_backward(const adr_scene*, const adr_camera*, const adr_render_params*,
+                                          const adr_frame*, const float*, adr_scene_grads*, adr_workspace*, void*) {
+  set_error("adr_render_backward: not implemented in this version");
+  return ADR_E_UNSUPPORTED;
+}
+
+extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n) {
+  if (!ws || !ms || n <= 0 || !ws->timing_valid) return 0;
+  if (hipEventSynchronize(ws->ev[7]) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int32_t k = 0;
+  for (; k < 7 && k < n; ++k) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ws->ev[k], ws->ev[k + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      t = -1.f;
+    }
+    ms[k] = t;
+  }
+  return k;
+}
+
+extern "C" int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n) {
+  if (!ws || !out || n <= 0) return 0;
+  if (hipStreamSynchronize(ws->last_stream) != hipSuccess ||
+      hipMemcpy(ws->host_counters, ws->dev_counters, kCounters * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  int32_t k = 0;
+  for (; k < 5 && k < n; ++k) out[k] = (int64_t)ws->host_counters[k];
+  return k;
+}

@@ -1,0 +1,266 @@
+// Preprocess (Sec. 3.2, stage 1) with the paper's early culling of
+// Gaussian-tile pairs (Sec. 4.2 adaptive radius, Eqs. 5-8; Sec. 4.3 AABB,
+// Eqs. 9-11). One lane per Gaussian.
+//
+// Every scalar that decides an integer (visibility, the pixel and tile
+// rectangles, tiles_touched, the depth key) is computed in FP64: the stage
+// is HBM-bound and gfx950 runs FP64 FMA at the non-packed FP32 lane rate,
+// so this costs little and keeps the integer outputs bit-exact against an
+// FP64 reference. The render record is rounded to FP32 at the end.
+#include "adr_internal.h"
+
+namespace adr {
+
+// Normalisation constants of the real SH basis, filled on the host from
+// N_lm = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!), times sqrt(2) for m != 0.
+struct ShConsts {
+  float k[16];
+};
+
+__device__ __forceinline__ void sh_colour(const float* __restrict__ planes, int64_t n, int64_t g, int n_coeff,
+                                          const ShConsts& kc, float x, float y, float z, float& r, float& gr,
+                                          float& b) {
+  // Polynomial parts P_l^|m|(cos th) cos(m ph) / sin(|m| ph) on the unit
+  // sphere, Condon-Shortley phase included; index l*l + l + m.
+  float basis[16];
+  basis[0] = 1.f;
+  if (n_coeff > 1) {
+    basis[1] = -y;
+    basis[2] = z;
+    basis[3] = -x;
+  }
+  if (n_coeff > 4) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    basis[4] = 6.f * x * y;
+    basis[5] = -3.f * z * y;
+    basis[6] = 0.5f * (3.f * zz - 1.f);
+    basis[7] = -3.f * z * x;
+    basis[8] = 3.f * (xx - yy);
+    if (n_coeff > 9) {
+      const float t = -1.5f * (5.f * zz - 1.f);
+      basis[9] = -15.f * (3.f * xx * y - yy * y);
+      basis[10] = 30.f * x * y * z;
+      basis[11] = t * y;
+      basis[12] = 0.5f * (5.f * zz * z - 3.f * z);
+      basis[13] = t * x;
+      basis[14] = 15.f * z * (xx - yy);
+      basis[15] = -15.f * (xx * x - 3.f * x * yy);
+    }
+  }
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int k = 0; k < n_coeff; ++k) {
+    const float w = kc.k[k] * basis[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = fmaf(w, planes[(int64_t)(3 * k + c) * n + g], acc[c]);
+  }
+  r = fmaxf(acc[0] + 0.5f, 0.f);
+  gr = fmaxf(acc[1] + 0.5f, 0.f);
+  b = fmaxf(acc[2] + 0.5f, 0.f);
+}
+
+__device__ __forceinline__ uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+
+// Clipped integer range of pixel centres in [c - r, c + r]; lo > hi when empty.
+__device__ __forceinline__ void pixel_span(double c, double r, int size, int& lo, int& hi) {
+  double l = ceil(c - r);
+  double h = floor(c + r);
+  l = fmax(l, 0.0);
+  h = fmin(h, (double)(size - 1));
+  if (!(l <= h)) {  // also catches NaN
+    lo = 1;
+    hi = 0;
+    return;
+  }
+  lo = (int)l;
+  hi = (int)h;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, off, 64);
+    hi = __shfl_xor(hi, off, 64);
+    v += ((unsigned long long)hi << 32) | lo;
+  }
+  return v;
+}
+
+__global__ void __launch_bounds__(256) preprocess_kernel(
+    const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
+    const float* __restrict__ planes, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, CullArgs cull,
+    RenderRecord* __restrict__ rec, ExactRecord* __restrict__ exact, uint2* __restrict__ tile_rect,
+    float* __restrict__ depth_out, uint32_t* __restrict__ touched_out, unsigned long long* __restrict__ counters) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t touched = 0;
+  if (g < n) {
+    const float4 ga = geo_a[g];
+    const double mx = ga.x, my = ga.y, mz = ga.z;
+    const double px = cam.r[0] * mx + cam.r[1] * my + cam.r[2] * mz + cam.t[0];
+    const double py = cam.r[3] * mx + cam.r[4] * my + cam.r[5] * mz + cam.t[1];
+    const double pz = cam.r[6] * mx + cam.r[7] * my + cam.r[8] * mz + cam.t[2];
+    if (pz > cam.near_z) {
+      const float4 gb = geo_b[g];
+      const float4 gq = geo_q[g];
+      // Sigma = R S S^T R^T (Sec. 3.1)
+      const double s0 = exp((double)gb.x), s1 = exp((double)gb.y), s2 = exp((double)gb.z);
+      double qw = gq.x, qx = gq.y, qy = gq.z, qz = gq.w;
+      const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+      qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+      const double R00 = 1 - 2 * (qy * qy + qz * qz), R01 = 2 * (qx * qy - qw * qz), R02 = 2 * (qx * qz + qw * qy);
+      const double R10 = 2 * (qx * qy + qw * qz), R11 = 1 - 2 * (qx * qx + qz * qz), R12 = 2 * (qy * qz - qw * qx);
+      const double R20 = 2 * (qx * qz - qw * qy), R21 = 2 * (qy * qz + qw * qx), R22 = 1 - 2 * (qx * qx + qy * qy);
+      const double M00 = R00 * s0, M01 = R01 * s1, M02 = R02 * s2;
+      const double M10 = R10 * s0, M11 = R11 * s1, M12 = R12 * s2;
+      const double M20 = R20 * s0, M21 = R21 * s1, M22 = R22 * s2;
+      const double S00 = M00 * M00 + M01 * M01 + M02 * M02;
+      const double S01 = M00 * M10 + M01 * M11 + M02 * M12;
+      const double S02 = M00 * M20 + M01 * M21 + M02 * M22;
+      const double S11 = M10 * M10 + M11 * M11 + M12 * M12;
+      const double S12 = M10 * M20 + M11 * M21 + M12 * M22;
+      const double S22 = M20 * M20 + M21 * M21 + M22 * M22;
+      // EWA: local affine approximation of the projection at the centre,
+      // evaluated at a clamped x/z, y/z (Sec. 3.1 cites EWA).
+      const double xt = pz * fmin(fmax(px / pz, -cam.lim_x), cam.lim_x);
+      const double yt = pz * fmin(fmax(py / pz, -cam.lim_y), cam.lim_y);
+      const double j00 = cam.fx / pz, j02 = -cam.fx * xt / (pz * pz);
+      const double j11 = cam.fy / pz, j12 = -cam.fy * yt / (pz * pz);
+      // T = J W (2 x 3), W the world-to-camera rotation
+      const double T00 = j00 * cam.r[0] + j02 * cam.r[6];
+      const double T01 = j00 * cam.r[1] + j02 * cam.r[7];
+      const double T02 = j00 * cam.r[2] + j02 * cam.r[8];
+      const double T10 = j11 * cam.r[3] + j12 * cam.r[6];
+      const double T11 = j11 * cam.r[4] + j12 * cam.r[7];
+      const double T12 = j11 * cam.r[5] + j12 * cam.r[8];
+      // U = T Sigma; Sigma' = U T^T + lowpass I
+      const double U00 = T00 * S00 + T01 * S01 + T02 * S02;
+      const double U01 = T00 * S01 + T01 * S11 + T02 * S12;
+      const double U02 = T00 * S02 + T01 * S12 + T02 * S22;
+      const double U10 = T10 * S00 + T11 * S01 + T12 * S02;
+      const double U11 = T10 * S01 + T11 * S11 + T12 * S12;
+      const double U12 = T10 * S02 + T11 * S12 + T12 * S22;
+      const double a = U00 * T00 + U01 * T01 + U02 * T02 + cull.lowpass;
+      const double b = U00 * T10 + U01 * T11 + U02 * T12;
+      const double c = U10 * T10 + U11 * T11 + U12 * T12 + cull.lowpass;
+      const double det = a * c - b * b;
+      if (det > 0.0) {
+        const double ca = c / det, cb = -b / det, cc = a / det;
+        // larger eigenvalue, cancellation-free form of mid + sqrt(mid^2 - det)
+        const double mid = 0.5 * (a + c);
+        const double hd = 0.5 * (a - c);
+        const double lam = mid + sqrt(hd * hd + b * b);
+        const double r_o = 3.0 * sqrt(lam);
+        const double x = cam.fx * px / pz + cam.cx - 0.5;
+        const double y = cam.fy * py / pz + cam.cy - 0.5;
+        const double op = 1.0 / (1.0 + exp(-(double)ga.w));
+        const bool reaches = op >= cull.alpha_low;
+        const double lnr = reaches ? log(op / cull.alpha_low) : 0.0;
+        // Radii of the cull mode.
+        bool keep = true;
+        double rx = r_o, ry = r_o;
+        if (cull.mode == ADR_CULL_ADAPTIVE) {
+          keep = reaches;
+          rx = ry = fmin(sqrt(2.0 * lam * lnr), r_o);
+        } else if (cull.mode == ADR_CULL_AABB) {
+          keep = reaches;
+          rx = fmin(sqrt(2.0 * a * lnr), r_o);
+          ry = fmin(sqrt(2.0 * c * lnr), r_o);
+        }
+        int i_lo = 1, i_hi = 0, j_lo = 1, j_hi = 0;
+        if (keep) {
+          pixel_span(x, rx, cam.width, i_lo, i_hi);
+          pixel_span(y, ry, cam.height, j_lo, j_hi);
+        }
+        if (i_lo <= i_hi && j_lo <= j_hi) {
+          const int tx_lo = i_lo / kTile, tx_hi = i_hi / kTile;
+          const int ty_lo = j_lo / kTile, ty_hi = j_hi / kTile;
+          touched = (uint32_t)(tx_hi - tx_lo + 1) * (uint32_t)(ty_hi - ty_lo + 1);
+          tile_rect[g] = make_uint2(pack16(tx_lo, tx_hi), pack16(ty_lo, ty_hi));
+          depth_out[g] = (float)pz;
+          // Pixels the alpha_low ellipse can reach, independent of the cull
+          // mode: the blend stage skips a Gaussian for an 8 x 8 quadrant that
+          // this box misses (every such pixel has alpha < alpha_low).
+          int bx_lo = 1, bx_hi = 0, by_lo = 1, by_hi = 0;
+          if (reaches) {
+            pixel_span(x, sqrt(2.0 * a * lnr), cam.width, bx_lo, bx_hi);
+            pixel_span(y, sqrt(2.0 * c * lnr), cam.height, by_lo, by_hi);
+          }
+          // SH colour from the viewing direction camera -> centre
+          double vx = mx - cam.cam_pos[0], vy = my - cam.cam_pos[1], vz = mz - cam.cam_pos[2];
+          const double vn = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
+          float cr, cg, cbl;
+          sh_colour(planes, n, g, n_coeff, shc, (float)(vx * vn), (float)(vy * vn), (float)(vz * vn), cr, cg, cbl);
+          const double nl2e = -0.5 * 1.4426950408889634074;  // -(1/2) log2(e)
+          RenderRecord rr;
+          rr.x = x;
+          rr.y = y;
+          rr.qa = (float)(nl2e * ca);
+          rr.qb = (float)(2.0 * nl2e * cb);
+          rr.qc = (float)(nl2e * cc);
+          rr.ql = (float)log2(op);
+          rr.r = cr;
+          rr.g = cg;
+          rr.b = cbl;
+          rr.box_x = pack16(bx_lo, bx_hi);
+          rr.box_y = pack16(by_lo, by_hi);
+          rr.pad[0] = rr.pad[1] = rr.pad[2] = 0u;
+          rec[g] = rr;
+          ExactRecord er;
+          er.ca = ca;
+          er.cb = cb;
+          er.cc = cc;
+          er.opacity = op;
+          exact[g] = er;
+        }
+      }
+    }
+    touched_out[g] = touched;
+  }
+  // Pair total (u64, exact) and visible count for the host.
+  __shared__ unsigned long long part[2][4];
+  const unsigned long long wt = wave_sum_u64(touched);
+  const unsigned long long wv = wave_sum_u64(touched > 0 ? 1ull : 0ull);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    part[0][wid] = wt;
+    part[1][wid] = wv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long st = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    const unsigned long long sv = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    if (st) atomicAdd(&counters[0], st);
+    if (sv) atomicAdd(&counters[1], sv);
+  }
+}
+
+static ShConsts make_sh_consts() {
+  ShConsts s{};
+  const double pi = 3.14159265358979323846;
+  auto fact = [](int v) {
+    double f = 1.0;
+    for (int i = 2; i <= v; ++i) f *= i;
+    return f;
+  };
+  for (int l = 0; l <= 3; ++l)
+    for (int m = -l; m <= l; ++m) {
+      const int am = m < 0 ? -m : m;
+      double k = sqrt((2.0 * l + 1.0) / (4.0 * pi) * fact(l - am) / fact(l + am));
+      if (m != 0) k *= sqrt(2.0);
+      s.k[l * l + l + m] = (float)k;
+    }
+  return s;
+}
+
+hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
+                             hipStream_t stream) {
+  if (s.n == 0) return hipSuccess;
+  static const ShConsts shc = make_sh_consts();
+  dim3 grid((unsigned)((s.n + 255) / 256));
+  preprocess_kernel<<<grid, 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc, cam, cull,
+                                              ws->rec, ws->exact, ws->tile_rect, ws->depth, ws->touched,
+                                              ws->dev_counters);
+  return hipGetLastError();
+}
+
+}  // namespace adr

@@ -1,0 +1,100 @@
+// InclusiveSum (Sec. 3.2, stage 2): offsets of each Gaussian's pairs.
+// Reduce-then-scan in three launches: per-block totals, one workgroup scans
+// the totals, each block rescans its 2048 entries with its prefix.
+#include "adr_internal.h"
+
+namespace adr {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 entries per block
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+// Inclusive scan of one value per thread over a 256-thread block; returns
+// the thread's inclusive prefix and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* smem4, uint32_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t s = wave_incl_scan(v, lane);
+  if (lane == 63) smem4[wid] = s;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wid; ++w) before += smem4[w];
+  *total = smem4[0] + smem4[1] + smem4[2] + smem4[3];
+  __syncthreads();
+  return s + before;
+}
+
+__global__ void __launch_bounds__(kScanThreads) block_totals_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                                    uint32_t* __restrict__ partials) {
+  __shared__ uint32_t smem[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += in[base + i];
+  uint32_t total;
+  (void)block_incl_scan(s, smem, &total);
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of the block totals, in place.
+__global__ void __launch_bounds__(kScanThreads) scan_partials_kernel(uint32_t* __restrict__ partials, int64_t nb) {
+  __shared__ uint32_t smem[4];
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const uint32_t v = i < nb ? partials[i] : 0u;
+    uint32_t total;
+    const uint32_t incl = block_incl_scan(v, smem, &total);
+    if (i < nb) partials[i] = carry + incl - v;
+    carry += total;
+  }
+}
+
+__global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_t* __restrict__ in, int64_t n,
+                                                                   const uint32_t* __restrict__ partials,
+                                                                   uint32_t* __restrict__ out) {
+  __shared__ uint32_t smem[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    s += v[i];
+  }
+  uint32_t total;
+  const uint32_t incl = block_incl_scan(s, smem, &total);
+  uint32_t run = partials[blockIdx.x] + incl - s;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    run += v[i];
+    if (base + i < n) out[base + i] = run;
+  }
+}
+
+}  // namespace
+
+int64_t inclusive_sum_partials(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
+                                hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = inclusive_sum_partials(n);
+  block_totals_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials);
+  scan_partials_kernel<<<1, kScanThreads, 0, stream>>>(partials, nb);
+  scan_blocks_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials, out);
+  return hipGetLastError();
+}
+
+}  // namespace adr

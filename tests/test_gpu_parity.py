@@ -1,0 +1,237 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Integer outputs (tiles_touched, pair count, sorted keys and ids, tile ranges,
+per-pixel load counters and their sums) must match bit for bit; images must
+agree within 2e-4 per channel. Runs on an MI355X only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import (Camera, scene_small, scene_clusters, camera_small, camera_orbit, camera_1080p)
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 2e-4
+MARGIN = 1e-9  # oracle decisions closer than this to a threshold are ambiguous even in FP64
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2409_08669_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def ws(P):
+    return P.Workspace()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def gpu_frame(P, ws, scene_gpu, cam, mode, debug=True, **kw):
+    params = P.RenderParams(cull=mode, **kw)
+    out = P.render_frame(scene_gpu, cam, params, ws=ws, debug=debug)
+    res = {k: (to_np(v) if hasattr(v, "cpu") else v) for k, v in out.items() if k != "workspace"}
+    for k in ("l_iter", "l_blend", "tiles_touched", "values", "ranges"):
+        if k in res:
+            res[k] = res[k].view(np.uint32)
+    if "keys" in res:
+        res["keys"] = res["keys"].view(np.uint64)
+    return res
+
+
+def oracle_params(mode, **kw):
+    return O.Params(cull=mode, **kw)
+
+
+def check_integer_stage(g, o, n):
+    np.testing.assert_array_equal(g["tiles_touched"][:n], o["tiles_touched"], err_msg="tiles_touched")
+    assert g["n_pairs"] == o["n_pairs"], (g["n_pairs"], o["n_pairs"])
+    np.testing.assert_array_equal(g["keys"], o["keys"], err_msg="sorted keys")
+    np.testing.assert_array_equal(g["values"], o["values"], err_msg="sorted ids")
+    np.testing.assert_array_equal(g["ranges"].reshape(-1, 2), o["ranges"], err_msg="tile ranges")
+
+
+def check_pixels(g, o, mask=None):
+    """Image within IMG_TOL; counters exact except where the oracle's own
+    decision margin is below MARGIN."""
+    if mask is None:
+        mask = np.ones(o["l_iter"].shape, dtype=bool)
+    diff = np.abs(g["image"] - o["image"])[:, mask]
+    assert diff.size == 0 or diff.max() <= IMG_TOL, f"image max |diff| {diff.max():.3e}"
+    ambiguous = (o["alpha_margin"] < MARGIN) | (o["t_margin"] < MARGIN)
+    ok = mask & ~ambiguous
+    bad_b = int((g["l_blend"][ok] != o["l_blend"][ok]).sum())
+    bad_i = int((g["l_iter"][ok] != o["l_iter"][ok]).sum())
+    assert bad_b == 0 and bad_i == 0, f"load counters differ at {bad_b} / {bad_i} pixels"
+    np.testing.assert_allclose(g["final_t"][mask], o["final_t"][mask], rtol=1e-3, atol=2e-6)
+    return int(ambiguous.sum())
+
+
+def check_load_sums(g, o):
+    lb = o["l_blend"].astype(np.int64)
+    li = o["l_iter"].astype(np.int64)
+    expect = [lb.sum(), (lb * lb).sum(), li.sum(), (li * li).sum()]
+    assert [int(v) for v in g["load_sums"]] == [int(v) for v in expect]
+
+
+@pytest.fixture(scope="module")
+def small(P):
+    s = scene_small(2000, seed=0)
+    return s, P.Scene.from_synth(s), camera_small()
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["3sigma", "adaptive", "aabb"])
+def test_small_scene_parity(P, ws, small, mode):
+    s, sg, cam = small
+    say(f"small scene 2000 G, 128x128, mode {mode}")
+    g = gpu_frame(P, ws, sg, cam, mode)
+    o = O.render_frame(s, cam, oracle_params(mode))
+    check_integer_stage(g, o, s.n)
+    check_pixels(g, o)
+    check_load_sums(g, o)
+
+
+def test_small_scene_modes_render_bitwise_identical(P, ws, small):
+    _, sg, cam = small
+    say("mode invariance, small scene")
+    outs = [gpu_frame(P, ws, sg, cam, m, debug=False) for m in (0, 1, 2)]
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o["image"], outs[0]["image"])
+        np.testing.assert_array_equal(o["l_blend"], outs[0]["l_blend"])
+        np.testing.assert_array_equal(o["final_t"], outs[0]["final_t"])
+    assert np.all(outs[0]["l_iter"] >= outs[1]["l_iter"]) and np.all(outs[1]["l_iter"] >= outs[2]["l_iter"])
+    assert outs[0]["n_pairs"] > outs[1]["n_pairs"] > outs[2]["n_pairs"]
+
+
+def test_ragged_image_and_count(P, ws):
+    s = scene_small(2001, seed=5)
+    cam = camera_small(130, 70)  # 9 x 5 tiles, partial last column and row
+    say("ragged 2001 G, 130x70")
+    sg = P.Scene.from_synth(s)
+    for mode in (0, 2):
+        g = gpu_frame(P, ws, sg, cam, mode, background=(0.1, 0.2, 0.3))
+        o = O.render_frame(s, cam, oracle_params(mode, background=(0.1, 0.2, 0.3)))
+        check_integer_stage(g, o, s.n)
+        check_pixels(g, o)
+        check_load_sums(g, o)
+
+
+def test_sh_degree3_scene_parity(P, ws):
+    s = scene_clusters(40_000, seed=3)
+    cam = camera_orbit(30.0, 20.0, 45.0, 320, 240)
+    say("SH3 40k G, 320x240")
+    sg = P.Scene.from_synth(s)
+    g = gpu_frame(P, ws, sg, cam, 2)
+    o = O.render_frame(s, cam, oracle_params(2))
+    check_integer_stage(g, o, s.n)
+    check_pixels(g, o)
+
+
+def test_load_balancing_cap_parity(P, ws, small):
+    s, sg, cam = small
+    for k in (1, 3):
+        say(f"load-balancing cap K={k}")
+        g = gpu_frame(P, ws, sg, cam, 2, lb_cap=k)
+        o = O.render_frame(s, cam, oracle_params(2, lb_cap=k))
+        check_pixels(g, o)
+        check_load_sums(g, o)
+        assert g["l_blend"].max() <= k
+
+
+def test_degenerate_scenes(P, ws):
+    cam = camera_small(64, 48)
+    say("empty scene")
+    empty = scene_small(0, seed=0)
+    g = gpu_frame(P, ws, P.Scene.from_synth(empty), cam, 2, background=(0.2, 0.4, 0.6))
+    assert g["n_pairs"] == 0
+    for c, v in enumerate((0.2, 0.4, 0.6)):
+        assert np.all(g["image"][c] == np.float32(v))
+    assert np.all(g["final_t"] == 1) and g["l_iter"].max() == 0
+    say("single Gaussian")
+    one = scene_small(1, seed=4)
+    one.means[:] = 0
+    one.log_scales[:] = -1.5
+    one.opacity_logits[:] = 2.0
+    g = gpu_frame(P, ws, P.Scene.from_synth(one), cam, 2)
+    o = O.render_frame(one, cam, oracle_params(2))
+    check_integer_stage(g, o, 1)
+    check_pixels(g, o)
+    say("all opacities below alpha_low")
+    low = scene_small(300, seed=6)
+    low.opacity_logits[:] = np.float32(math.log((0.9 / 255) / (1 - 0.9 / 255)))
+    for mode in (0, 1, 2):
+        g = gpu_frame(P, ws, P.Scene.from_synth(low), cam, mode)
+        o = O.render_frame(low, cam, oracle_params(mode))
+        check_integer_stage(g, o, low.n)
+        assert np.all(g["image"] == 0) and g["l_blend"].max() == 0
+    say("everything behind the camera")
+    behind = scene_small(300, seed=7)
+    behind.means[:, 2] = -10.0
+    g = gpu_frame(P, ws, P.Scene.from_synth(behind), cam, 0)
+    assert g["n_pairs"] == 0 and np.all(g["tiles_touched"] == 0)
+
+
+def test_pair_capacity_too_small_reports_workspace_error(P, ws, small):
+    import torch
+    _, sg, cam = small
+    say("pair capacity error path")
+    img = torch.empty((3, cam.height, cam.width), device="cuda")
+    keys = torch.empty(10, dtype=torch.int64, device="cuda")
+    vals = torch.empty(10, dtype=torch.int32, device="cuda")
+    with pytest.raises(P.AdrError) as ei:
+        P.render(sg, cam, P.RenderParams(), ws, img, keys=keys, values=vals, pair_capacity=10)
+    assert ei.value.status == -5 and ei.value.n_pairs > 10
+
+
+def test_repeat_runs_are_bitwise_identical(P, ws, small):
+    _, sg, cam = small
+    say("determinism")
+    a = gpu_frame(P, ws, sg, cam, 2)
+    b = gpu_frame(P, ws, sg, cam, 2)
+    for k in ("image", "final_t", "l_iter", "l_blend", "keys", "values", "ranges", "load_sums"):
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+
+
+@pytest.mark.slow
+def test_headline_scale_integer_stage_and_sampled_tiles(P, ws):
+    """1M Gaussians, SH3, 1920x1080: the full integer stage bit-exact, and the
+    image and counters on 48 seeded tiles against the oracle."""
+    s = scene_clusters(1_000_000, seed=0)
+    cam = camera_1080p()
+    sg = P.Scene.from_synth(s)
+    pre = O.preprocess(s, cam, O.Params())
+    rng = np.random.default_rng(11)
+    tx_n, ty_n = O.n_tiles(cam)
+    for mode in (0, 2):
+        say(f"1M G 1080p mode {mode}")
+        g = gpu_frame(P, ws, sg, cam, mode)
+        params = oracle_params(mode)
+        rects = O.tile_rects(pre, cam, params)
+        keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+        ranges = O.tile_ranges(keys, cam)
+        o = dict(tiles_touched=rects["tiles_touched"], n_pairs=int(keys.size), keys=keys, values=values,
+                 ranges=ranges)
+        check_integer_stage(g, o, s.n)
+        busy = np.argsort(ranges[:, 1] - ranges[:, 0])[-16:]
+        tiles = np.unique(np.concatenate([rng.choice(tx_n * ty_n, 32, replace=False), busy]))
+        r = O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+        n_amb = check_pixels(g, r, mask=r["done"])
+        say(f"  pairs {g['n_pairs']}  sampled tiles {tiles.size}  ambiguous pixels {n_amb}")
+    say("1M G 1080p: 3-sigma and AABB images bitwise identical")
+    a = gpu_frame(P, ws, sg, cam, 0, debug=False)
+    b = gpu_frame(P, ws, sg, cam, 2, debug=False)
+    np.testing.assert_array_equal(a["image"], b["image"])
+    np.testing.assert_array_equal(a["l_blend"], b["l_blend"])
