@@ -1,0 +1,217 @@
+"""Frames/s of the forward rasterizer at 1080p with 1M Gaussians (SH degree 3),
+adaptive radius + AABB culling vs the plain 3-sigma radius, on one MI355X.
+
+A step is one whole frame through the C ABI: Preprocess with early culling,
+InclusiveSum, DuplicateWithKeys, SortPairs, IdentifyTileRanges and Render with
+the per-pixel load counters and their sums (Eq. 13). The scene and camera are
+resident in HBM before the timed region. Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frames/s at 1080p/1M Gaussians, adaptive vs 3σ radius; serving p99 ms"
+HBM_PEAK_GBS = 8000.0
+# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=48)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(stage, n, n_vis, n_pairs, n_pix, n_tiles, n_coeff, n_pass):
+    """Bytes the method itself must move per launch of each stage (reads +
+    writes), independent of how the kernel caches them."""
+    if stage == "preprocess":
+        # geometry of every Gaussian (48 B) + SH of visible ones + count out +
+        # render record (64 B) + FP64 record (32 B) + rect/depth (12 B) of visible ones
+        return n * 48 + n_vis * (12 * n_coeff) + n * 4 + n_vis * (64 + 32 + 12)
+    if stage == "inclusive_sum":
+        return n * 8
+    if stage == "duplicate":
+        return n_vis * 20 + n_pairs * 12
+    if stage == "sort":
+        return n_pairs * 8 + n_pass * n_pairs * 24  # histogram read + per pass read/write of key+id
+    if stage == "ranges":
+        return n_pairs * 8 + n_tiles * 8
+    if stage == "render":
+        # ids + 64-byte records of every pair, image + T + two counters out
+        return n_pairs * (4 + 64) + n_pix * 24
+    return 0
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (a multi-GPU split is "
+                                   "described, not implemented)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2409_08669_amd as P
+    from paper_2409_08669_amd.binding import STAGES
+    from synth import scene_clusters, camera_1080p
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load()
+    log(f"generating scene: {args.n} Gaussians, SH degree 3, seed {args.seed}")
+    scene = scene_clusters(args.n, seed=args.seed)
+    cam = camera_1080p()
+    sg = P.Scene.from_synth(scene)
+    ws = P.Workspace()
+    w, h = cam.width, cam.height
+    dev = "cuda"
+    out = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
+               l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
+               l_blend=torch.empty((h, w), dtype=torch.int32, device=dev),
+               load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
+    stream = torch.cuda.current_stream()
+    n_tiles = ((w + 15) // 16) * ((h + 15) // 16)
+    n_pass = math.ceil((32 + math.ceil(math.log2(n_tiles))) / 8)
+
+    # name: (cull mode, extra flags). The last one is an ablation: the paper's
+    # AABB pair culling alone, without reusing the extent inside Render.
+    modes = {"3sigma": (P.ADR_CULL_3SIGMA, 0), "adaptive": (P.ADR_CULL_ADAPTIVE, 0),
+             "aabb": (P.ADR_CULL_AABB, 0), "aabb_pairs_only": (P.ADR_CULL_AABB, P.ADR_FLAG_NO_QUAD_CULL)}
+    results = {}
+    images = {}
+    for name, (mode, extra) in modes.items():
+        params = P.RenderParams(cull=mode, flags=P.ADR_FLAG_TIMING | extra)
+        log(f"mode {name}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            P.render(sg, cam, params, ws, **out)
+        torch.cuda.synchronize()
+        stage_sum = {s: 0.0 for s in STAGES}
+        log(f"mode {name}: timing {args.steps} frames")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            n_pairs = P.render(sg, cam, params, ws, **out)
+            st = ws.stage_times()
+            for k, v in st.items():
+                stage_sum[k] += v
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        counters = ws.counters()
+        sums = out["load_sums"].cpu().numpy()
+        mean_b, std_b = P.load_stats_from_sums(sums[0:2], w * h)
+        mean_i, std_i = P.load_stats_from_sums(sums[2:4], w * h)
+        results[name] = dict(
+            fps=args.steps / dt, ms_per_frame=1e3 * dt / args.steps, pairs=int(n_pairs),
+            visible=counters.get("visible"), stages_ms={k: v / args.steps for k, v in stage_sum.items()},
+            band_redecisions=counters.get("band_redecisions"), t_replays=counters.get("t_replays"),
+            load_mean_blend=mean_b, load_std_blend=std_b, load_mean_iter=mean_i, load_std_iter=std_i)
+        images[name] = out["image"].clone()
+        log(f"mode {name}: {results[name]['fps']:.1f} frames/s, pairs {n_pairs}, stages "
+            + ", ".join(f"{k} {v:.3f}" for k, v in results[name]["stages_ms"].items()))
+    identical = all(bool(torch.equal(images["3sigma"], im)) for im in images.values())
+
+    # Roofline of the dominant kernel stage of the headline (AABB) frame.
+    head = results["aabb"]
+    n_vis = head["visible"] or args.n
+    kern = {k: v for k, v in head["stages_ms"].items() if k != "host_wait"}
+    dom = max(kern, key=kern.get)
+    traffic = algorithmic_bytes(dom, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, n_pass)
+    achieved = traffic / (kern[dom] * 1e-3) / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes": int(traffic), "avg_ms": round(kern[dom], 4)}
+    per_stage = {}
+    for s_, ms in kern.items():
+        b = algorithmic_bytes(s_, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, n_pass)
+        per_stage[s_] = {"ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                         "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cam, args.cpu_tiles, n_tiles)
+
+    line = {
+        "metric": METRIC,
+        "value": round(head["fps"], 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_frame"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M Gaussians (64-cluster mixture, SH degree 3), one 1920x1080 orbit camera, "
+                               "adaptive-radius+AABB culling (3-sigma and adaptive also timed)",
+                   "n_gaussians": args.n, "width": w, "height": h, "sh_degree": 3, "cull": "aabb",
+                   "alpha_low": 1.0 / 255.0, "seed": args.seed},
+        "modes": {k: {"fps": round(v["fps"], 2), "ms_per_frame": round(v["ms_per_frame"], 4),
+                      "pairs_per_frame": v["pairs"], "stages_ms": {s_: round(x, 4) for s_, x in v["stages_ms"].items()},
+                      "load_std_blend": round(v["load_std_blend"], 4), "load_std_iter": round(v["load_std_iter"], 4),
+                      "band_redecisions": v["band_redecisions"], "t_replays": v["t_replays"]}
+                  for k, v in results.items()},
+        "speedup_aabb_vs_3sigma": round(results["aabb"]["fps"] / results["3sigma"]["fps"], 4),
+        "speedup_adaptive_vs_3sigma": round(results["adaptive"]["fps"] / results["3sigma"]["fps"], 4),
+        "identical_output_across_modes": identical,
+        "stages": per_stage,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "serving_p99_ms": None,
+        "paper_context": "paper reports ~3.1x over 3DGS (Ours-Full, RTX 3090, trained scenes); AABB alone 1.65-2.11x",
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(scene, cam, n_tiles_sample, n_tiles):
+    """The FP64 oracle on the host: full preprocess, pair emission and sort of
+    the whole frame, and the blend of a seeded sample of tiles, extrapolated
+    to all tiles."""
+    import numpy as np
+
+    import oracle as O
+
+    log(f"cpu baseline: oracle preprocess + sort of the full frame, blend of {n_tiles_sample} tiles")
+    params = O.Params(cull=O.CULL_AABB)
+    t0 = time.perf_counter()
+    pre = O.preprocess(scene, cam, params)
+    rects = O.tile_rects(pre, cam, params)
+    keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+    ranges = O.tile_ranges(keys, cam)
+    t1 = time.perf_counter()
+    rng = np.random.default_rng(123)
+    tiles = rng.choice(n_tiles, size=min(n_tiles_sample, n_tiles), replace=False)
+    O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+    t2 = time.perf_counter()
+    per_frame = (t1 - t0) + (t2 - t1) * n_tiles / len(tiles)
+    return {"value": round(1.0 / per_frame, 6), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "seconds_per_frame": round(per_frame, 2),
+            "sample": f"FP64 NumPy oracle, one thread: preprocess+emission+sort of all {scene.n} Gaussians "
+                      f"({t1 - t0:.1f} s) and the blend of {len(tiles)} seeded tiles of {n_tiles} "
+                      f"({t2 - t1:.1f} s), blend time extrapolated by tile count",
+            "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

@@ -40,6 +40,10 @@ typedef enum {
 } adr_status;
 
 /* Pair culling of the Preprocess stage. */
+/* The adaptive and AABB modes also reuse their (uncapped) extent inside the
+ * Render stage: a wave skips a Gaussian for an 8 x 8 pixel quadrant that the
+ * extent misses. The 3-sigma baseline evaluates every entry of a tile's list
+ * for every pixel of the tile. All three give the same image. */
 typedef enum {
   ADR_CULL_3SIGMA = 0,   /* baseline: square of radius r_o = 3 sqrt(lambda'_max) (Sec. 4.2) */
   ADR_CULL_ADAPTIVE = 1, /* r = min(sqrt(2 lambda'_max ln(sigma/alpha_low)), r_o) (Eqs. 7-8) */
@@ -91,6 +95,8 @@ typedef struct {
 #define ADR_FLAG_TIMING 1u      /* record per-stage HIP events; see adr_workspace_stage_times */
 #define ADR_FLAG_NO_EXACT_BAND 2u /* skip the FP64 re-decision of near-threshold alphas and
                                      transmittances (faster, no longer bit-matched to FP64) */
+#define ADR_FLAG_NO_QUAD_CULL 4u  /* adaptive/AABB modes: cull Gaussian-tile pairs only, and evaluate
+                                     every list entry for every pixel of the tile (ablation; same output) */
 
 typedef struct {
   int32_t cull;      /* adr_cull */
@@ -173,7 +179,8 @@ int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
 
 /* Per-frame counters of the last adr_render on ws (host values; the frame
  * must have finished): [0] pairs, [1] visible Gaussians (tiles_touched > 0),
- * [2] exact-band alpha re-decisions, [3] exact-band transmittance replays. */
+ * [2] exact-band alpha re-decisions, [3] exact-band transmittance replays,
+ * [4] reserved (0). Returns the number of entries written. */
 int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n);
 
 const char* adr_last_error(void);

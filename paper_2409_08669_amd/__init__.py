@@ -10,6 +10,7 @@ from .binding import (  # noqa: F401
     ADR_CULL_AABB,
     ADR_FLAG_TIMING,
     ADR_FLAG_NO_EXACT_BAND,
+    ADR_FLAG_NO_QUAD_CULL,
     AdrError,
     RenderParams,
     Scene,

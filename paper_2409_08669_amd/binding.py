@@ -28,6 +28,7 @@ ADR_CULL_AABB = 2
 
 ADR_FLAG_TIMING = 1
 ADR_FLAG_NO_EXACT_BAND = 2
+ADR_FLAG_NO_QUAD_CULL = 4
 
 STAGES = ("preprocess", "inclusive_sum", "host_wait", "duplicate", "sort", "ranges", "render")
 

@@ -38,12 +38,13 @@ struct DeviceScene {
 // with (qa, qb, qc) = -(1/2) log2(e) (conic_a, 2 conic_b, conic_c) and
 // ql = log2(opacity); dx = x - i, dy = y - j for pixel (i, j).
 struct alignas(16) RenderRecord {
+  uint32_t box_x;         // lo | hi << 16: pixel columns that may have alpha >= alpha_low
+  uint32_t box_y;         // lo | hi << 16: pixel rows (lo > hi: none)
+  uint32_t pad0, pad1;
   double x, y;            // projected centre, pixel centres at integers
   float qa, qb, qc, ql;
   float r, g, b;
-  uint32_t box_x;         // lo | hi << 16: pixel columns the alpha_low ellipse can reach
-  uint32_t box_y;         // lo | hi << 16: pixel rows (lo > hi: none)
-  uint32_t pad[3];
+  uint32_t pad2;
 };
 static_assert(sizeof(RenderRecord) == 64, "render record is four 16-byte loads");
 
@@ -69,6 +70,7 @@ struct CamArgs {
 
 struct CullArgs {
   int32_t mode;
+  int32_t quad_cull;        // render-side 8 x 8 quadrant cull in the culling modes
   double alpha_low;
   double lowpass;
 };
@@ -116,6 +118,10 @@ struct adr_workspace {
   adr::SortBuffers sort;
   uint32_t* ranges = nullptr;      // 2 * tiles
   int64_t ranges_capacity = 0;
+  uint32_t* tile_order = nullptr;  // render order of the tiles, longest lists first
+  int64_t tile_order_capacity = 0;
+  unsigned long long* wave_sums = nullptr;  // 4 x u64 per render wave (load-sum partials)
+  int64_t wave_sums_capacity = 0;
   unsigned long long* dev_counters = nullptr; // [0] pairs, [1] visible, [2] band, [3] replays, [4] sort spin limit
   unsigned long long* host_counters = nullptr; // pinned mirror
   hipEvent_t ev[8] = {};
@@ -154,8 +160,9 @@ int64_t sort_hist_entries(int64_t n_pairs);
 hipError_t launch_tile_ranges(const uint64_t* keys, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
-                         const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
-                         const BlendArgs& blend, adr_frame* out, unsigned long long* counters, hipStream_t stream);
+                         const uint32_t* ranges, uint32_t* order, void* wave_sums, int64_t n_pairs,
+                         int64_t n_gauss, const CamArgs& cam, const BlendArgs& blend, adr_frame* out,
+                         unsigned long long* counters, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 

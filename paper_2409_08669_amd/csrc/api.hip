@@ -135,7 +135,7 @@ extern "C" void adr_workspace_destroy(adr_workspace* ws) {
   (void)hipDeviceSynchronize();
   void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->depth, ws->touched, ws->offsets, ws->scan_partials,
                   ws->sort.keys[0], ws->sort.keys[1], ws->sort.vals[0], ws->sort.vals[1], ws->sort.block_hist,
-                  ws->ranges, ws->dev_counters};
+                  ws->ranges, ws->tile_order, ws->wave_sums, ws->dev_counters};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ws->host_counters) (void)hipHostFree(ws->host_counters);
@@ -216,6 +216,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
 
   CullArgs cu{};
   cu.mode = p->cull;
+  cu.quad_cull = (p->flags & ADR_FLAG_NO_QUAD_CULL) ? 0 : 1;
   cu.alpha_low = p->alpha_low;
   cu.lowpass = p->lowpass;
 
@@ -224,17 +225,26 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   bl.t_min = (float)p->t_min;
   bl.q_low = (float)std::log2(p->alpha_low);
   bl.q_band = 1.0f / 4096.0f;  // FP32 q carries ~1e-5 error; the band is >20x that
-  bl.t_band_lo = (float)(p->t_min * (1.0 - 1.0 / 256.0));
-  bl.t_band_hi = (float)(p->t_min * (1.0 + 1.0 / 256.0));
+  // FP32 transmittance drifts from FP64 by at most ~2e-5 relative per blend
+  // (alpha near 0.99 is the worst case); the band is ~50x a single blend's error
+  bl.t_band_lo = (float)(p->t_min * (1.0 - 1.0 / 1024.0));
+  bl.t_band_hi = (float)(p->t_min * (1.0 + 1.0 / 1024.0));
   bl.alpha_low_d = p->alpha_low;
   bl.alpha_max_d = p->alpha_max;
   bl.t_min_d = p->t_min;
   for (int c = 0; c < 3; ++c) bl.bg[c] = p->background[c];
   bl.lb_cap = p->lb_cap;
   bl.exact = (p->flags & ADR_FLAG_NO_EXACT_BAND) ? 0 : 1;
+  if (!bl.exact) {  // empty bands: the FP32 decisions stand
+    bl.q_band = 0.f;
+    bl.t_band_lo = 1.f;
+    bl.t_band_hi = 0.f;
+  }
 
   if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
   if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;
+  if ((st = grow(ws->tile_order, ws->tile_order_capacity, n_tiles, "tile order")) != ADR_OK) return st;
+  if ((st = grow(ws->wave_sums, ws->wave_sums_capacity, 16 * n_tiles, "load-sum partials")) != ADR_OK) return st;
   const bool timing = (p->flags & ADR_FLAG_TIMING) != 0;
   ws->timing_valid = false;
   ws->last_stream = stream;
@@ -278,8 +288,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ADR_HIP(launch_tile_ranges(keys, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
   // Stage 6: Render
-  if (out->load_sums) ADR_HIP(launch_fill_u64((unsigned long long*)out->load_sums, 0ull, 4, stream));
-  ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, n_pairs, s.n, ca, bl, out, ws->dev_counters, stream));
+  ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, ws->wave_sums, n_pairs, s.n, ca,
+                        bl, out, ws->dev_counters, stream));
   if (timing) {
     ADR_HIP(hipEventRecord(ws->ev[7], stream));
     ws->timing_valid = true;

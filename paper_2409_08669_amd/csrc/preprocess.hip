@@ -177,13 +177,18 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
           touched = (uint32_t)(tx_hi - tx_lo + 1) * (uint32_t)(ty_hi - ty_lo + 1);
           tile_rect[g] = make_uint2(pack16(tx_lo, tx_hi), pack16(ty_lo, ty_hi));
           depth_out[g] = (float)pz;
-          // Pixels the alpha_low ellipse can reach, independent of the cull
-          // mode: the blend stage skips a Gaussian for an 8 x 8 quadrant that
-          // this box misses (every such pixel has alpha < alpha_low).
-          int bx_lo = 1, bx_hi = 0, by_lo = 1, by_hi = 0;
-          if (reaches) {
-            pixel_span(x, sqrt(2.0 * a * lnr), cam.width, bx_lo, bx_hi);
-            pixel_span(y, sqrt(2.0 * c * lnr), cam.height, by_lo, by_hi);
+          // Render-side cull box. The blend stage skips a Gaussian for an 8 x 8
+          // quadrant that this box misses. In the culling modes it is the
+          // mode's extent without the r_o cap (Eq. 7 square, or Eq. 10 box),
+          // which contains the whole alpha_low ellipse, so every skipped pixel
+          // has alpha < alpha_low. The 3-sigma baseline has no such extent:
+          // its box is the whole image and every list entry is evaluated.
+          int bx_lo = 0, bx_hi = cam.width - 1, by_lo = 0, by_hi = cam.height - 1;
+          if (cull.mode != ADR_CULL_3SIGMA && cull.quad_cull) {
+            const double ex = cull.mode == ADR_CULL_AABB ? sqrt(2.0 * a * lnr) : sqrt(2.0 * lam * lnr);
+            const double ey = cull.mode == ADR_CULL_AABB ? sqrt(2.0 * c * lnr) : ex;
+            pixel_span(x, ex, cam.width, bx_lo, bx_hi);
+            pixel_span(y, ey, cam.height, by_lo, by_hi);
           }
           // SH colour from the viewing direction camera -> centre
           double vx = mx - cam.cam_pos[0], vy = my - cam.cam_pos[1], vz = mz - cam.cam_pos[2];
@@ -203,7 +208,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
           rr.b = cbl;
           rr.box_x = pack16(bx_lo, bx_hi);
           rr.box_y = pack16(by_lo, by_hi);
-          rr.pad[0] = rr.pad[1] = rr.pad[2] = 0u;
+          rr.pad0 = rr.pad1 = rr.pad2 = 0u;
           rec[g] = rr;
           ExactRecord er;
           er.ca = ca;

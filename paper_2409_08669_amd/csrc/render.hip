@@ -4,35 +4,33 @@
 //
 // Layout: one 256-lane workgroup per 16 x 16 tile; each wave64 owns an 8 x 8
 // quadrant and walks the tile's depth-sorted list on its own, so a quadrant
-// whose pixels are all saturated stops without waiting for the others.
-// Batches of 64 list entries are loaded one per lane (ids, then 64-byte
-// records); a ballot marks the entries whose alpha_low box meets the
-// quadrant and only those are evaluated, each broadcast to the wave with
-// readlane. Entries outside the box are exactly the ones whose alpha is below
-// alpha_low for every pixel of the quadrant, so skipping them changes nothing.
+// whose pixels are all saturated stops without waiting for the others. Per
+// batch of 64 list entries every lane loads one id and that Gaussian's
+// alpha_low box (8 bytes); a ballot marks the entries whose box meets the
+// quadrant, and only those lanes load the rest of the record into the wave's
+// LDS slots, compacted by their rank in the ballot. The wave then evaluates
+// the compacted entries in list order, reading each with broadcast LDS loads.
+// An entry outside the box has alpha < alpha_low at every pixel of the
+// quadrant, so skipping it changes nothing.
 //
 // Precision: the record centre is made quadrant-relative in FP64 before the
-// FP32 evaluation. The skip decision alpha < alpha_low and the stop decision
-// T < t_min are re-taken in FP64 when the FP32 values fall inside a narrow
-// band around the threshold, so the blended sequence matches an FP64
-// evaluation of the same definition.
+// FP32 evaluation. The skip decision alpha < alpha_low is re-taken in FP64
+// when the FP32 exponent falls in a narrow band around log2(alpha_low); when
+// a transmittance lands in a narrow band around t_min the whole wave
+// recomputes that pixel's transmittance in FP64 over the list so far, and the
+// stop decision uses that value. The blended sequence and the load counters
+// therefore follow an FP64 evaluation of the same definition.
 #include "adr_internal.h"
 
 namespace adr {
 
 namespace {
 
-__device__ __forceinline__ float bcast_f(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-__device__ __forceinline__ uint32_t bcast_u(uint32_t v, int lane) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
-}
-__device__ __forceinline__ double bcast_d(double v, int lane) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const uint32_t lo = bcast_u((uint32_t)u, lane), hi = bcast_u((uint32_t)(u >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
+struct alignas(16) Staged {
+  float4 a;  // x - qx0, y - qy0, qa, qb
+  float4 b;  // qc, ql, r, g
+  float4 c;  // b, gid bits, list index bits, 0
+};
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
@@ -45,7 +43,23 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
-// FP64 splatting opacity of Gaussian g at pixel (pi, pj) (Eq. 2), clamped.
+__device__ __forceinline__ double wave_prod_f64(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    lo = __shfl_xor(lo, off, 64);
+    hi = __shfl_xor(hi, off, 64);
+    v *= __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
+  return v;
+}
+
+__device__ __forceinline__ bool box_has(uint32_t bx, uint32_t by, int i, int j) {
+  return (int)(bx & 0xffffu) <= i && (int)(bx >> 16) >= i && (int)(by & 0xffffu) <= j && (int)(by >> 16) >= j;
+}
+
+// FP64 splatting opacity at pixel (pi, pj) (Eq. 2), clamped at alpha_max.
 __device__ __forceinline__ double alpha_fp64(const ExactRecord& e, double x, double y, int pi, int pj,
                                              double alpha_max) {
   const double dx = x - (double)pi, dy = y - (double)pj;
@@ -53,47 +67,96 @@ __device__ __forceinline__ double alpha_fp64(const ExactRecord& e, double x, dou
   return fmin(alpha_max, e.opacity * exp(power));
 }
 
-// Transmittance of pixel (pi, pj) after list entries [s, k_end], in FP64.
-__device__ double replay_fp64(const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact,
-                              const uint32_t* __restrict__ vals, uint32_t n_gauss, uint32_t s, uint32_t k_end,
-                              int pi, int pj, const BlendArgs& bl) {
-  double t = 1.0;
-  for (uint32_t k = s; k <= k_end; ++k) {
-    const uint32_t g = min(vals[k], n_gauss - 1);
-    const uint32_t bx = rec[g].box_x, by = rec[g].box_y;
-    if ((int)(bx & 0xffffu) > pi || (int)(bx >> 16) < pi || (int)(by & 0xffffu) > pj || (int)(by >> 16) < pj)
-      continue;  // outside the alpha_low ellipse: alpha < alpha_low
-    const double a = alpha_fp64(exact[g], rec[g].x, rec[g].y, pi, pj, bl.alpha_max_d);
-    if (a < bl.alpha_low_d) continue;
-    t *= 1.0 - a;
+// FP64 alpha of Gaussian g at pixel (pi, pj); kept out of line so the rare
+// FP64 path does not raise the register count of the blend loop.
+__device__ __noinline__ double alpha_fp64_at(const RenderRecord* __restrict__ rec,
+                                             const ExactRecord* __restrict__ exact, uint32_t g, int pi, int pj,
+                                             double alpha_max) {
+  return alpha_fp64(exact[g], rec[g].x, rec[g].y, pi, pj, alpha_max);
+}
+
+// log2-domain exponent of a staged Gaussian at the lane's pixel (lx, ly)
+__device__ __forceinline__ float quad_form(const float4& A, const float4& B, float fx, float fy) {
+  const float dx = A.x - fx, dy = A.y - fy;
+  return fmaf(A.z * dx, dx, fmaf(A.w * dx, dy, fmaf(B.x * dy, dy, B.y)));
+}
+
+// FP64 transmittance of pixel (ri, rj) after list entries [s, k_now]: the
+// wave's lanes take every 64th entry and the partial products are combined.
+__device__ __noinline__ double replay_fp64(const RenderRecord* __restrict__ rec,
+                                           const ExactRecord* __restrict__ exact,
+                                           const uint32_t* __restrict__ vals, uint32_t n_gauss, uint32_t s,
+                                           uint32_t k_now, int ri, int rj, int lane, const BlendArgs& bl) {
+  double prod = 1.0;
+  for (uint32_t kk = s + lane; kk <= k_now; kk += 64) {
+    const uint32_t gg = min(vals[kk], n_gauss - 1);
+    const RenderRecord& rr = rec[gg];
+    if (!box_has(rr.box_x, rr.box_y, ri, rj)) continue;
+    const double ad = alpha_fp64(exact[gg], rr.x, rr.y, ri, rj, bl.alpha_max_d);
+    if (ad >= bl.alpha_low_d) prod *= 1.0 - ad;
   }
-  return t;
+  return wave_prod_f64(prod);
+}
+
+// Longest lists first: workgroups start in launch order, so the tiles whose
+// waves run longest (the heavy-load pixels of Sec. 4.4) start first and the
+// short ones fill in around them. Buckets of floor(log2(length)), longest
+// bucket first; the order inside a bucket does not affect any output.
+constexpr int kOrderBuckets = 33;
+constexpr uint32_t kLongList = 1024;
+
+__global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                          uint32_t n_pairs, uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[kOrderBuckets];
+  __shared__ uint32_t off[kOrderBuckets];
+  if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const uint32_t e = min(ranges[2 * t + 1], n_pairs), s = min(ranges[2 * t], e);
+    const uint32_t len = e - s;
+    const int b = len == 0 ? kOrderBuckets - 1 : (kOrderBuckets - 2) - (31 - __clz(len));
+    atomicAdd(&cnt[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+      off[b] = run;
+      run += cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const uint32_t e = min(ranges[2 * t + 1], n_pairs), s = min(ranges[2 * t], e);
+    const uint32_t len = e - s;
+    const int b = len == 0 ? kOrderBuckets - 1 : (kOrderBuckets - 2) - (31 - __clz(len));
+    order[atomicAdd(&off[b], 1u)] = (uint32_t)t;
+  }
 }
 
 __global__ void __launch_bounds__(256) render_kernel(
     const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, uint32_t n_pairs, uint32_t n_gauss, CamArgs cam, BlendArgs bl,
-    int n_tiles, int per_xcd,
-    float* __restrict__ image, float* __restrict__ final_t, uint32_t* __restrict__ l_iter,
-    uint32_t* __restrict__ l_blend, unsigned long long* __restrict__ load_sums,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, uint32_t n_pairs, uint32_t n_gauss,
+    CamArgs cam, BlendArgs bl, int n_tiles, float* __restrict__ image, float* __restrict__ final_t,
+    uint32_t* __restrict__ l_iter, uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums,
     unsigned long long* __restrict__ counters) {
-  // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so
-  // give each XCD a contiguous band of tiles (neighbouring tiles share
-  // Gaussians, which then stay in that XCD's L2).
-  const int bid = blockIdx.x;
-  const int tile = (bid & 7) * per_xcd + (bid >> 3);
-  if (tile >= n_tiles) return;
+  __shared__ Staged stage[4][64];
+  const int tile = (int)min(order[blockIdx.x], (uint32_t)(n_tiles - 1));
   const int W = cam.width, H = cam.height;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int qx0 = tx * kTile + (wid & 1) * kQuad;
   const int qy0 = ty * kTile + (wid >> 1) * kQuad;
-  if (qx0 >= W || qy0 >= H) return;  // quadrant entirely outside the image (wave-uniform)
+  if (qx0 >= W || qy0 >= H) {  // quadrant entirely outside the image (wave-uniform)
+    if (wave_sums && lane == 0) wave_sums[4 * tile + wid] = make_ulonglong4(0ull, 0ull, 0ull, 0ull);
+    return;
+  }
   const int qx1 = min(qx0 + kQuad - 1, W - 1), qy1 = min(qy0 + kQuad - 1, H - 1);
   const int lx = lane & 7, ly = lane >> 3;
   const int pi = qx0 + lx, pj = qy0 + ly;
   const bool inside = pi < W && pj < H;
   const float fx = (float)lx, fy = (float)ly;
+  Staged* my = stage[wid];
 
   // ranges come from this frame's sorted keys; the clamps only make a
   // corrupted table unable to send a load outside the buffers
@@ -101,79 +164,120 @@ __global__ void __launch_bounds__(256) render_kernel(
   const uint32_t s = min(ranges[2 * tile], e);
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   uint32_t nb = 0;
-  int64_t stop_k = -1;
+  uint32_t stop_k = 0xffffffffu;
   bool done = !inside;
   uint32_t n_band = 0, n_replay = 0;
+  const uint32_t cap = bl.lb_cap > 0 ? (uint32_t)bl.lb_cap : 0xffffffffu;
+  // The longest lists bound the kernel's duration: let their waves issue
+  // first on a shared SIMD (wave priority only; no effect on results).
+  if (e - s >= kLongList) __builtin_amdgcn_s_setprio(3);
 
+  // Two-deep software pipeline over batches: while batch b is evaluated the
+  // boxes of batch b+1 and the ids of batch b+2 are in flight.
+  const uint2 kNoBox = make_uint2(1u, 1u);  // lo 1 > hi 0: empty
+  uint32_t g_cur = s + lane < e ? min(vals[s + lane], n_gauss - 1) : 0u;
+  uint2 box_cur = s + lane < e ? *reinterpret_cast<const uint2*>(&rec[g_cur].box_x) : kNoBox;
+  uint32_t g_next = s + 64 + lane < e ? min(vals[s + 64 + lane], n_gauss - 1) : 0u;
   for (uint32_t base = s; base < e; base += 64) {
     const uint32_t k = base + lane;
-    const bool valid = k < e;
-    uint32_t g = 0;
-    RenderRecord r;
-    bool hit = false;
-    if (valid) {
-      g = min(vals[k], n_gauss - 1);
-      r = rec[g];
-      hit = (int)(r.box_x & 0xffffu) <= qx1 && (int)(r.box_x >> 16) >= qx0 && (int)(r.box_y & 0xffffu) <= qy1 &&
-            (int)(r.box_y >> 16) >= qy0;
-    } else {
-      r = RenderRecord{};
+    const uint32_t g = g_cur;
+    const uint2 box = box_cur;
+    const bool hit = (int)(box.x & 0xffffu) <= qx1 && (int)(box.x >> 16) >= qx0 && (int)(box.y & 0xffffu) <= qy1 &&
+                     (int)(box.y >> 16) >= qy0;
+    const uint64_t mask = __ballot(hit);
+    if (hit) {
+      const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      const RenderRecord& r = rec[g];
+      const double x = r.x, y = r.y;
+      const float4 q = *reinterpret_cast<const float4*>(&r.qa);
+      const float4 c = *reinterpret_cast<const float4*>(&r.r);
+      Staged st;
+      st.a = make_float4((float)(x - (double)qx0), (float)(y - (double)qy0), q.x, q.y);
+      st.b = make_float4(q.z, q.w, c.x, c.y);
+      st.c = make_float4(c.z, __uint_as_float(g), __uint_as_float(k), 0.f);
+      my[slot] = st;
     }
-    // centre relative to the quadrant origin, computed in FP64
-    const float xr = valid ? (float)(r.x - (double)qx0) : 0.f;
-    const float yr = valid ? (float)(r.y - (double)qy0) : 0.f;
-    uint64_t mask = __ballot(hit);
-    while (mask) {
-      const int j = __builtin_ctzll(mask);
-      mask &= mask - 1;
-      const float gx = bcast_f(xr, j), gy = bcast_f(yr, j);
-      const float qa = bcast_f(r.qa, j), qb = bcast_f(r.qb, j), qc = bcast_f(r.qc, j), ql = bcast_f(r.ql, j);
-      const float c0 = bcast_f(r.r, j), c1 = bcast_f(r.g, j), c2 = bcast_f(r.b, j);
-      if (!done) {
-        const float dx = gx - fx, dy = gy - fy;
-        const float q = fmaf(qa * dx, dx, fmaf(qb * dx, dy, fmaf(qc * dy, dy, ql)));
-        bool blend = q >= bl.q_low;
-        float a = 0.f;
-        if (bl.exact && fabsf(q - bl.q_low) < bl.q_band) {
-          // near alpha_low: decide in FP64
-          const uint32_t gj = bcast_u(g, j);
-          const double xd = bcast_d(r.x, j), yd = bcast_d(r.y, j);
-          const double ad = alpha_fp64(exact[gj], xd, yd, pi, pj, bl.alpha_max_d);
+    // issue the next loads before evaluating this batch
+    {
+      const uint32_t k1 = base + 64 + lane, k2 = base + 128 + lane;
+      g_cur = g_next;
+      box_cur = k1 < e ? *reinterpret_cast<const uint2*>(&rec[g_next].box_x) : kNoBox;
+      g_next = k2 < e ? min(vals[k2], n_gauss - 1) : 0u;
+    }
+    if (mask == 0) continue;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int n_hit = __popcll(mask);
+    // Pipeline: the exponent of entry i+1 is computed while entry i is
+    // blended (it does not depend on the transmittance).
+    float4 A = stage[wid][0].a, B = stage[wid][0].b, C = stage[wid][0].c;
+    float q = quad_form(A, B, fx, fy);
+    float e2 = __builtin_amdgcn_exp2f(q);
+    for (int i = 0; i < n_hit; ++i) {
+      const int inext = min(i + 1, n_hit - 1);
+      const float4 An = stage[wid][inext].a, Bn = stage[wid][inext].b, Cn = stage[wid][inext].c;
+      const float qn = quad_form(An, Bn, fx, fy);
+      const float e2n = __builtin_amdgcn_exp2f(qn);
+
+      float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
+      bool blend = !done && q >= bl.q_low;
+      float Tn = T * (1.f - a);
+      bool near_t = blend && Tn >= bl.t_band_lo && Tn <= bl.t_band_hi;
+      const bool near_low = !done && fabsf(q - bl.q_low) < bl.q_band;
+      float t_exact = 0.f;
+      bool stop_exact = false;
+      if (__builtin_expect(__ballot(near_low || near_t) != 0, 0)) {
+        // Rare (wave-uniform branch): an exponent near log2(alpha_low) is
+        // decided in FP64; a transmittance near t_min is recomputed in FP64
+        // by the whole wave over the list so far.
+        if (near_low) {
+          const double ad = alpha_fp64_at(rec, exact, __float_as_uint(C.y), pi, pj, bl.alpha_max_d);
           blend = ad >= bl.alpha_low_d;
           a = (float)ad;
+          Tn = T * (1.f - a);
+          near_t = blend && Tn >= bl.t_band_lo && Tn <= bl.t_band_hi;
           ++n_band;
-        } else if (blend) {
-          a = fminf(bl.alpha_max, __builtin_amdgcn_exp2f(q));
         }
-        if (blend) {
-          const float w = a * T;
-          cr = fmaf(c0, w, cr);
-          cg = fmaf(c1, w, cg);
-          cb = fmaf(c2, w, cb);
-          T = T * (1.f - a);
-          ++nb;
-          bool stop = T < bl.t_min;
-          if (bl.exact && T >= bl.t_band_lo && T <= bl.t_band_hi) {
-            // near t_min: re-run this pixel's list up to here in FP64
-            const double td = replay_fp64(rec, exact, vals, n_gauss, s, base + (uint32_t)j, pi, pj, bl);
-            stop = td < bl.t_min_d;
-            T = (float)td;
+        uint64_t rm = __ballot(near_t);
+        const uint32_t k_now = __float_as_uint(C.z);
+        while (rm) {
+          const int L = __builtin_ctzll(rm);
+          rm &= rm - 1;
+          const int ri = __builtin_amdgcn_readlane(pi, L), rj = __builtin_amdgcn_readlane(pj, L);
+          const double prod = replay_fp64(rec, exact, vals, n_gauss, s, k_now, ri, rj, lane, bl);
+          if (lane == L) {
+            t_exact = (float)prod;
+            stop_exact = prod < bl.t_min_d;
             ++n_replay;
-          }
-          if (!stop && bl.lb_cap > 0 && nb == (uint32_t)bl.lb_cap) stop = true;
-          if (stop) {
-            done = true;
-            stop_k = (int64_t)base + j;
           }
         }
       }
-      if (__ballot(!done) == 0) goto finished;
+      const float w = blend ? a * T : 0.f;
+      cr = fmaf(B.z, w, cr);
+      cg = fmaf(B.w, w, cg);
+      cb = fmaf(C.x, w, cb);
+      T = blend ? (near_t ? t_exact : Tn) : T;
+      nb += blend ? 1u : 0u;
+      // bitwise on purpose: no short-circuit branches in the common path
+      const bool t_stop = near_t ? stop_exact : (T < bl.t_min);
+      const bool stop = blend & (t_stop | (nb == cap));
+      stop_k = stop ? __float_as_uint(C.z) : stop_k;
+      done = done || stop;
+      A = An;
+      B = Bn;
+      C = Cn;
+      q = qn;
+      e2 = e2n;
     }
+    if (__ballot(!done) == 0) goto finished;
+    __builtin_amdgcn_wave_barrier();  // all reads of this batch's slots before the next writes
   }
 finished:
   uint32_t ni = 0;
   if (inside) {
-    ni = stop_k >= 0 ? (uint32_t)(stop_k - (int64_t)s + 1) : e - s;
+    ni = stop_k != 0xffffffffu ? stop_k - s + 1 : e - s;
     const int64_t pix = (int64_t)pj * W + pi;
     const int64_t plane = (int64_t)W * H;
     image[pix] = cr + T * bl.bg[0];
@@ -183,15 +287,12 @@ finished:
     if (l_iter) l_iter[pix] = ni;
     if (l_blend) l_blend[pix] = nb;
   }
-  if (load_sums) {
+  if (wave_sums) {
+    // per-wave partial sums for Eq. 13; reduced in a fixed order afterwards
+    // (one address per wave: no contended atomics, and reproducible)
     const unsigned long long b1 = wave_sum_u64(nb), b2 = wave_sum_u64((unsigned long long)nb * nb);
     const unsigned long long i1 = wave_sum_u64(ni), i2 = wave_sum_u64((unsigned long long)ni * ni);
-    if (lane == 0) {
-      if (b1) atomicAdd(&load_sums[0], b1);
-      if (b2) atomicAdd(&load_sums[1], b2);
-      if (i1) atomicAdd(&load_sums[2], i1);
-      if (i2) atomicAdd(&load_sums[3], i2);
-    }
+    if (lane == 0) wave_sums[4 * tile + wid] = make_ulonglong4(b1, b2, i1, i2);
   }
   if (counters) {
     const unsigned long long nbd = wave_sum_u64(n_band), nrp = wave_sum_u64(n_replay);
@@ -202,17 +303,50 @@ finished:
   }
 }
 
+// Sums the per-wave partials into the four load sums, in a fixed order.
+__global__ void __launch_bounds__(1024) load_sums_kernel(const ulonglong4* __restrict__ wave_sums, int n,
+                                                         unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[16][4];
+  unsigned long long a = 0, b = 0, c = 0, d = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const ulonglong4 v = wave_sums[i];
+    a += v.x;
+    b += v.y;
+    c += v.z;
+    d += v.w;
+  }
+  a = wave_sum_u64(a);
+  b = wave_sum_u64(b);
+  c = wave_sum_u64(c);
+  d = wave_sum_u64(d);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    part[wid][0] = a;
+    part[wid][1] = b;
+    part[wid][2] = c;
+    part[wid][3] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
-                         const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
-                         const BlendArgs& blend, adr_frame* out, unsigned long long* counters, hipStream_t stream) {
+                         const uint32_t* ranges, uint32_t* order, void* wave_sums, int64_t n_pairs,
+                         int64_t n_gauss, const CamArgs& cam, const BlendArgs& blend, adr_frame* out,
+                         unsigned long long* counters, hipStream_t stream) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  const int per_xcd = (n_tiles + 7) / 8;
-  render_kernel<<<dim3((unsigned)(8 * per_xcd)), 256, 0, stream>>>(
-      rec, exact, vals, ranges, (uint32_t)n_pairs, (uint32_t)(n_gauss > 0 ? n_gauss : 1), cam, blend, n_tiles,
-      per_xcd, out->image, out->final_t, out->l_iter, out->l_blend,
-      (unsigned long long*)out->load_sums, counters);
+  ulonglong4* ws4 = out->load_sums ? (ulonglong4*)wave_sums : nullptr;
+  tile_order_kernel<<<1, 1024, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, order);
+  render_kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(
+      rec, exact, vals, ranges, order, (uint32_t)n_pairs, (uint32_t)(n_gauss > 0 ? n_gauss : 1), cam, blend,
+      n_tiles, out->image, out->final_t, out->l_iter, out->l_blend, ws4, counters);
+  if (ws4) load_sums_kernel<<<1, 1024, 0, stream>>>(ws4, 4 * n_tiles, (unsigned long long*)out->load_sums);
   return hipGetLastError();
 }
 

@@ -3,12 +3,14 @@
 // id bits), 8 bits per pass.
 //
 // One histogram launch reads the keys once and counts the digits of every
-// pass. Each pass is then a single launch in the "onesweep" style (Adinets &
-// Merrill 2022): a workgroup ranks 4096 keys in LDS, publishes its per-digit
-// counts, obtains the counts of all earlier workgroups by decoupled
-// look-back, and scatters. Ranking is stable and uses wave64 ballots: the
-// lanes of a row that share a digit are found with eight ballots, one per
-// digit bit, and counted with popcounts, so no LDS atomics decide an order.
+// pass. Each pass is reduce-then-scan: per-workgroup digit counts, one
+// workgroup per digit scans them into scatter offsets, and a downsweep ranks
+// 4096 keys per workgroup in LDS and scatters. A decoupled look-back would
+// save the count read, but across the eight XCDs its serial chain of
+// device-coherent loads cost ~0.5 ms per pass; every step here is parallel.
+// Ranking is stable and uses wave64 ballots: the lanes of a row that share a
+// digit are found with eight ballots, one per digit bit, and counted with
+// popcounts, so no LDS atomics decide an order.
 #include "adr_internal.h"
 
 namespace adr {
@@ -20,10 +22,6 @@ constexpr int kItems = 16;
 constexpr int kTileKeys = kThreads * kItems;  // 4096 keys per workgroup
 constexpr int kRadix = 256;
 constexpr int kMaxPasses = 8;
-constexpr uint32_t kFlagAggregate = 1u << 30;
-constexpr uint32_t kFlagInclusive = 2u << 30;
-constexpr uint32_t kValueMask = (1u << 30) - 1;
-constexpr uint32_t kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 #pragma unroll
@@ -62,26 +60,68 @@ __global__ void __launch_bounds__(kThreads) digit_histogram_kernel(const uint64_
   }
 }
 
-__global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint64_t* __restrict__ kin,
-                                                            const uint32_t* __restrict__ vin,
-                                                            uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                            int64_t n, int shift, const uint32_t* __restrict__ hist,
-                                                            uint32_t* __restrict__ status,
-                                                            uint32_t* __restrict__ tile_counter,
-                                                            unsigned long long* __restrict__ err) {
+// Per-workgroup digit counts of one pass: counts[d * nb + b].
+__global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint64_t* __restrict__ kin, int64_t n, int shift,
+                                                           uint32_t* __restrict__ counts, int64_t nb) {
+  __shared__ uint32_t wh[4][kRadix];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int i = tid; i < 4 * kRadix; i += kThreads) (&wh[0][0])[i] = 0u;
+  __syncthreads();
+  const int64_t wave_base = (int64_t)blockIdx.x * kTileKeys + (int64_t)wid * (kItems * 64);
+#pragma unroll 4
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t idx = wave_base + r * 64 + lane;
+    if (idx < n) atomicAdd(&wh[wid][(uint32_t)(kin[idx] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  counts[(int64_t)tid * nb + blockIdx.x] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
+}
+
+// One workgroup per digit d: offsets[d * nb + b] = (keys with a smaller digit)
+// + (keys with digit d in earlier workgroups).
+__global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __restrict__ counts, int64_t nb,
+                                                                 const uint32_t* __restrict__ hist) {
+  __shared__ uint32_t scan_tmp[4];
+  const int d = blockIdx.x;
+  // digit base: exclusive prefix of the global histogram at d
+  const uint32_t base = block_excl_scan(hist[threadIdx.x], scan_tmp);
+  __shared__ uint32_t s_base;
+  if ((int)threadIdx.x == d) s_base = base;
+  __syncthreads();
+  uint32_t carry = s_base;
+  uint32_t* row = counts + (int64_t)d * nb;
+  for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
+    const int64_t b = b0 + threadIdx.x;
+    const uint32_t v = b < nb ? row[b] : 0u;
+    const uint32_t ex = block_excl_scan(v, scan_tmp);
+    __shared__ uint32_t s_last;
+    if (threadIdx.x == kThreads - 1) s_last = ex + v;
+    __syncthreads();
+    if (b < nb) row[b] = carry + ex;
+    carry += s_last;
+    __syncthreads();
+  }
+}
+
+// Stable rank of the workgroup's 4096 keys and scatter to the offsets of
+// the pass.
+__global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint64_t* __restrict__ kin,
+                                                             const uint32_t* __restrict__ vin,
+                                                             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             int64_t n, int shift, const uint32_t* __restrict__ offsets,
+                                                             int64_t nb) {
   __shared__ uint64_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
   __shared__ uint32_t wcnt[4][kRadix];
   __shared__ uint32_t blk_start[kRadix];
   __shared__ uint32_t glob_base[kRadix];
   __shared__ uint32_t scan_tmp[4];
-  __shared__ uint32_t s_bid;
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) s_bid = atomicAdd(tile_counter, 1u);
+  const uint32_t bid = blockIdx.x;
   for (int i = tid; i < 4 * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0u;
+  glob_base[tid] = offsets[(int64_t)tid * nb + bid];
   __syncthreads();
-  const uint32_t bid = s_bid;
   const int64_t wave_base = (int64_t)bid * kTileKeys + (int64_t)wid * (kItems * 64);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -94,7 +134,13 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint64_t* __re
     const bool valid = idx < n;
     k[r] = valid ? kin[idx] : ~0ull;
     v[r] = valid ? vin[idx] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const int64_t idx = wave_base + r * 64 + lane;
+    const bool valid = idx < n;
     const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
+    // lanes of this row holding the same digit, from one ballot per digit bit
     uint64_t m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -111,44 +157,14 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint64_t* __re
   }
   __syncthreads();
 
-  // Per digit: offsets of the four waves and the workgroup total.
+  // Per digit: offsets of the four waves and the workgroup's digit starts.
   const int d = tid;
   const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
-  const uint32_t tot = c0 + c1 + c2 + c3;
   wcnt[0][d] = 0u;
   wcnt[1][d] = c0;
   wcnt[2][d] = c0 + c1;
   wcnt[3][d] = c0 + c1 + c2;
-  uint32_t* my_status = status + (int64_t)bid * kRadix + d;
-  __hip_atomic_store(my_status, (bid == 0 ? kFlagInclusive : kFlagAggregate) | tot, __ATOMIC_RELEASE,
-                     __HIP_MEMORY_SCOPE_AGENT);
-  blk_start[d] = block_excl_scan(tot, scan_tmp);
-  const uint32_t digit_base = block_excl_scan(hist[d], scan_tmp);
-
-  // Decoupled look-back over earlier workgroups, one digit per thread.
-  uint32_t excl = 0;
-  if (bid > 0) {
-    int64_t j = (int64_t)bid - 1;
-    uint32_t spins = 0;
-    while (true) {
-      const uint32_t s = __hip_atomic_load(status + j * kRadix + d, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t flag = s & ~kValueMask;
-      if (flag == 0u) {
-        if (++spins > kSpinLimit) {  // never expected; guarantees termination
-          atomicAdd(err, 1ull);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        continue;
-      }
-      excl += s & kValueMask;
-      if (flag == kFlagInclusive || j == 0) break;
-      --j;
-    }
-    __hip_atomic_store(my_status, kFlagInclusive | (excl + tot), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  glob_base[d] = digit_base + excl;
-  __syncthreads();
+  blk_start[d] = block_excl_scan(c0 + c1 + c2 + c3, scan_tmp);  // contains the barrier
 
   // Stable local order in LDS, then a coalesced scatter per digit run.
 #pragma unroll
@@ -179,8 +195,8 @@ __global__ void __launch_bounds__(kThreads) onesweep_kernel(const uint64_t* __re
 
 int64_t sort_hist_entries(int64_t n_pairs) {
   const int64_t nb = (n_pairs + kTileKeys - 1) / kTileKeys;
-  // per pass: status[nb][256], then counters[kMaxPasses], hist[kMaxPasses][256]
-  return (int64_t)kMaxPasses * nb * kRadix + kMaxPasses + kMaxPasses * kRadix;
+  // digit counts / offsets [256][nb], then the global histograms [kMaxPasses][256]
+  return (int64_t)kRadix * nb + kMaxPasses * kRadix;
 }
 
 hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* result_buffer,
@@ -190,11 +206,9 @@ hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* 
   const int n_pass = (n_bits + 7) / 8;
   if (n_pass > kMaxPasses) return hipErrorInvalidValue;
   const int64_t nb = (n_pairs + kTileKeys - 1) / kTileKeys;
-  uint32_t* status = sb.block_hist;
-  uint32_t* counters = status + (int64_t)kMaxPasses * nb * kRadix;
-  uint32_t* hist = counters + kMaxPasses;
-  hipError_t e = launch_fill_u32(sb.block_hist, 0u, (int64_t)n_pass * nb * kRadix, stream);
-  if (e == hipSuccess) e = launch_fill_u32(counters, 0u, kMaxPasses + kMaxPasses * kRadix, stream);
+  uint32_t* counts = sb.block_hist;
+  uint32_t* hist = counts + (int64_t)kRadix * nb;
+  hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kRadix, stream);
   if (e != hipSuccess) return e;
   int64_t hist_blocks = (n_pairs + kThreads * 16 - 1) / (kThreads * 16);
   if (hist_blocks > 2048) hist_blocks = 2048;
@@ -202,9 +216,10 @@ hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* 
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int p = 0; p < n_pass; ++p) {
-    onesweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(
-        sb.keys[cur], sb.vals[cur], sb.keys[cur ^ 1], sb.vals[cur ^ 1], n_pairs, 8 * p, hist + p * kRadix,
-        status + (int64_t)p * nb * kRadix, counters + p, sb.err);
+    upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(sb.keys[cur], n_pairs, 8 * p, counts, nb);
+    digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, hist + p * kRadix);
+    downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(sb.keys[cur], sb.vals[cur], sb.keys[cur ^ 1],
+                                                                    sb.vals[cur ^ 1], n_pairs, 8 * p, counts, nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }

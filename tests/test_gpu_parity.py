@@ -116,6 +116,19 @@ def test_small_scene_modes_render_bitwise_identical(P, ws, small):
     assert outs[0]["n_pairs"] > outs[1]["n_pairs"] > outs[2]["n_pairs"]
 
 
+def test_ablation_flags_keep_the_output(P, ws, small):
+    """Disabling the render-side quadrant cull changes no output bit;
+    disabling the FP64 bands keeps the image within tolerance."""
+    s, sg, cam = small
+    say("ablation flags")
+    ref = gpu_frame(P, ws, sg, cam, 2, debug=False)
+    nq = gpu_frame(P, ws, sg, cam, 2, debug=False, flags=P.ADR_FLAG_NO_QUAD_CULL)
+    for k in ("image", "final_t", "l_iter", "l_blend", "load_sums"):
+        np.testing.assert_array_equal(nq[k], ref[k], err_msg=k)
+    nb = gpu_frame(P, ws, sg, cam, 2, debug=False, flags=P.ADR_FLAG_NO_EXACT_BAND)
+    assert np.abs(nb["image"] - ref["image"]).max() <= IMG_TOL
+
+
 def test_ragged_image_and_count(P, ws):
     s = scene_small(2001, seed=5)
     cam = camera_small(130, 70)  # 9 x 5 tiles, partial last column and row
