@@ -23,8 +23,15 @@ if ROOT not in sys.path:
 
 METRIC = "frames/s at 1080p/1M Gaussians, adaptive vs 3σ radius; serving p99 ms"
 HBM_PEAK_GBS = 8000.0
-# VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s
-VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# FP32 VALU without packed instructions: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# x 2 flops per FMA = 78.6 TFLOP/s (the 157.3 TFLOP/s headline needs packed FP32)
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# Flops of the blend definition (Eq. 2-3): per examined list entry, the offset
+# (2), the quadratic form (3 mul + 3 fma = 9), exp (1), clamp (1) and the
+# alpha_low test (1); per blended entry, the weight (1), three colour FMAs (6),
+# 1 - alpha and the transmittance product (2) and the stop test (1).
+FLOPS_PER_EXAMINED = 14
+FLOPS_PER_BLENDED = 10
 
 
 def log(msg):
@@ -39,7 +46,11 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=48)
+    ap.add_argument("--cpu-tiles", type=int, default=2048)
+    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only"], default=None,
+                    help="time one mode only (for profiler runs)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (scales HBM counters)")
     return ap.parse_args()
 
 
@@ -61,6 +72,10 @@ def algorithmic_bytes(stage, n, n_vis, n_pairs, n_pix, n_tiles, n_coeff, n_pass)
     if stage == "render":
         # ids + 64-byte records of every pair, image + T + two counters out
         return n_pairs * (4 + 64) + n_pix * 24
+    if stage == "tile_order":
+        return n_tiles * (8 + 4)
+    if stage == "load_sums":
+        return n_tiles * 4 * 32
     return 0
 
 
@@ -98,6 +113,8 @@ def main():
     # AABB pair culling alone, without reusing the extent inside Render.
     modes = {"3sigma": (P.ADR_CULL_3SIGMA, 0), "adaptive": (P.ADR_CULL_ADAPTIVE, 0),
              "aabb": (P.ADR_CULL_AABB, 0), "aabb_pairs_only": (P.ADR_CULL_AABB, P.ADR_FLAG_NO_QUAD_CULL)}
+    if args.only:
+        modes = {args.only: modes[args.only]}
     results = {}
     images = {}
     for name, (mode, extra) in modes.items():
@@ -122,29 +139,56 @@ def main():
         mean_i, std_i = P.load_stats_from_sums(sums[2:4], w * h)
         results[name] = dict(
             fps=args.steps / dt, ms_per_frame=1e3 * dt / args.steps, pairs=int(n_pairs),
+            sum_blend=int(sums[0]), sum_iter=int(sums[2]),
             visible=counters.get("visible"), stages_ms={k: v / args.steps for k, v in stage_sum.items()},
             band_redecisions=counters.get("band_redecisions"), t_replays=counters.get("t_replays"),
             load_mean_blend=mean_b, load_std_blend=std_b, load_mean_iter=mean_i, load_std_iter=std_i)
         images[name] = out["image"].clone()
         log(f"mode {name}: {results[name]['fps']:.1f} frames/s, pairs {n_pairs}, stages "
             + ", ".join(f"{k} {v:.3f}" for k, v in results[name]["stages_ms"].items()))
-    identical = all(bool(torch.equal(images["3sigma"], im)) for im in images.values())
+    first = next(iter(images.values()))
+    identical = all(bool(torch.equal(first, im)) for im in images.values())
+    if args.copy_probe_mib:
+        n_el = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n_el, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+    if args.only:
+        r = results[args.only]
+        print(json.dumps({"mode": args.only, "fps": round(r["fps"], 2), "pairs": r["pairs"],
+                          "stages_ms": {k: round(v, 4) for k, v in r["stages_ms"].items()}}), flush=True)
+        return
 
-    # Roofline of the dominant kernel stage of the headline (AABB) frame.
+    # Roofline of the dominant kernel of the headline (AABB) frame. The blend
+    # kernel is bound by FP32 VALU work: its algorithmic work is the paper's
+    # pixel-parallel cost, sum over pixels of the list entries examined
+    # (l_iter) and blended (l_blend), both exact from the frame's load sums.
     head = results["aabb"]
     n_vis = head["visible"] or args.n
     kern = {k: v for k, v in head["stages_ms"].items() if k != "host_wait"}
     dom = max(kern, key=kern.get)
-    traffic = algorithmic_bytes(dom, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, n_pass)
-    achieved = traffic / (kern[dom] * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_bytes": int(traffic), "avg_ms": round(kern[dom], 4)}
     per_stage = {}
     for s_, ms in kern.items():
         b = algorithmic_bytes(s_, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, n_pass)
-        per_stage[s_] = {"ms": round(ms, 4), "GB/s": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+        per_stage[s_] = {"ms": round(ms, 4), "algorithmic_bytes": int(b),
+                         "GB/s": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                          "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+    if dom == "render":
+        flops = FLOPS_PER_EXAMINED * head["sum_iter"] + FLOPS_PER_BLENDED * head["sum_blend"]
+        achieved = flops / (kern[dom] * 1e-3) / 1e12
+        roofline = {"kernel": "render_kernel", "bound": "alu", "achieved": round(achieved, 3),
+                    "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "algorithmic_flops": int(flops), "examined": head["sum_iter"], "blended": head["sum_blend"],
+                    "avg_ms": round(kern[dom], 4)}
+    else:
+        b = per_stage[dom]["algorithmic_bytes"]
+        achieved = b / (kern[dom] * 1e-3) / 1e9
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "algorithmic_bytes": int(b), "avg_ms": round(kern[dom], 4)}
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -124,7 +124,8 @@ struct adr_workspace {
   int64_t wave_sums_capacity = 0;
   unsigned long long* dev_counters = nullptr; // [0] pairs, [1] visible, [2] band, [3] replays, [4] sort spin limit
   unsigned long long* host_counters = nullptr; // pinned mirror
-  hipEvent_t ev[8] = {};
+  static constexpr int kEvents = 10;
+  hipEvent_t ev[kEvents] = {};
   bool timing_valid = false;
   hipStream_t last_stream = nullptr;
   int64_t last_pairs = 0;
@@ -159,10 +160,13 @@ hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* 
 int64_t sort_hist_entries(int64_t n_pairs);
 hipError_t launch_tile_ranges(const uint64_t* keys, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order,
+                             hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
-                         const uint32_t* ranges, uint32_t* order, void* wave_sums, int64_t n_pairs,
+                         const uint32_t* ranges, const uint32_t* order, void* wave_sums, int64_t n_pairs,
                          int64_t n_gauss, const CamArgs& cam, const BlendArgs& blend, adr_frame* out,
                          unsigned long long* counters, hipStream_t stream);
+hipError_t launch_load_sums(const void* wave_sums, int n_tiles, uint64_t* load_sums, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 

@@ -115,7 +115,7 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
   }
   std::memset(ws->host_counters, 0, kCounters * sizeof(unsigned long long));
   ws->sort.err = ws->dev_counters + 4;
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < adr_workspace::kEvents; ++i) {
     if (hipEventCreate(&ws->ev[i]) != hipSuccess) {
       (void)hipGetLastError();
       set_error("adr_workspace_create: hipEventCreate failed");
@@ -287,11 +287,15 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   // Stage 5: IdentifyTileRanges
   ADR_HIP(launch_tile_ranges(keys, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
-  // Stage 6: Render
+  // Stage 6: Render (tile order, blend, load sums)
+  ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[7], stream));
   ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, ws->wave_sums, n_pairs, s.n, ca,
                         bl, out, ws->dev_counters, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
+  ADR_HIP(launch_load_sums(ws->wave_sums, (int)n_tiles, out->load_sums, stream));
   if (timing) {
-    ADR_HIP(hipEventRecord(ws->ev[7], stream));
+    ADR_HIP(hipEventRecord(ws->ev[9], stream));
     ws->timing_valid = true;
   }
 
@@ -324,12 +328,12 @@ extern "C" adr_status adr_render_backward(const adr_scene*, const adr_camera*, c
 
 extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n) {
   if (!ws || !ms || n <= 0 || !ws->timing_valid) return 0;
-  if (hipEventSynchronize(ws->ev[7]) != hipSuccess) {
+  if (hipEventSynchronize(ws->ev[adr_workspace::kEvents - 1]) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   int32_t k = 0;
-  for (; k < 7 && k < n; ++k) {
+  for (; k < adr_workspace::kEvents - 1 && k < n; ++k) {
     float t = 0.f;
     if (hipEventElapsedTime(&t, ws->ev[k], ws->ev[k + 1]) != hipSuccess) {
       (void)hipGetLastError();

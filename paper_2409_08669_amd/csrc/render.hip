@@ -336,17 +336,28 @@ __global__ void __launch_bounds__(1024) load_sums_kernel(const ulonglong4* __res
 
 }  // namespace
 
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order,
+                             hipStream_t stream) {
+  tile_order_kernel<<<1, 1024, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
-                         const uint32_t* ranges, uint32_t* order, void* wave_sums, int64_t n_pairs,
+                         const uint32_t* ranges, const uint32_t* order, void* wave_sums, int64_t n_pairs,
                          int64_t n_gauss, const CamArgs& cam, const BlendArgs& blend, adr_frame* out,
                          unsigned long long* counters, hipStream_t stream) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   ulonglong4* ws4 = out->load_sums ? (ulonglong4*)wave_sums : nullptr;
-  tile_order_kernel<<<1, 1024, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, order);
   render_kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(
       rec, exact, vals, ranges, order, (uint32_t)n_pairs, (uint32_t)(n_gauss > 0 ? n_gauss : 1), cam, blend,
       n_tiles, out->image, out->final_t, out->l_iter, out->l_blend, ws4, counters);
-  if (ws4) load_sums_kernel<<<1, 1024, 0, stream>>>(ws4, 4 * n_tiles, (unsigned long long*)out->load_sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_sums(const void* wave_sums, int n_tiles, uint64_t* load_sums, hipStream_t stream) {
+  if (!load_sums) return hipSuccess;
+  load_sums_kernel<<<1, 1024, 0, stream>>>((const ulonglong4*)wave_sums, 4 * n_tiles,
+                                           (unsigned long long*)load_sums);
   return hipGetLastError();
 }
 
