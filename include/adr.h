@@ -172,9 +172,10 @@ adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, co
                                adr_workspace* ws, void* stream);
 
 /* Stage durations (ms) of the last adr_render on ws that had ADR_FLAG_TIMING:
- * [0] preprocess, [1] inclusive sum, [2] host wait for the pair count,
- * [3] duplicate with keys, [4] sort, [5] tile ranges, [6] tile render order,
- * [7] render (the blend kernel alone), [8] load-sum reduction.
+ * [0] preprocess, [1] host wait for the pair count, [2] depth sort of the
+ * Gaussians, [3] inclusive sum, [4] duplicate with keys, [5] tile sort of the
+ * pairs, [6] tile ranges, [7] tile render order, [8] render (the blend kernel
+ * alone), [9] load-sum reduction.
  * Waits for the frame to finish. Returns the number of stages written. */
 int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
 

@@ -30,8 +30,8 @@ ADR_FLAG_TIMING = 1
 ADR_FLAG_NO_EXACT_BAND = 2
 ADR_FLAG_NO_QUAD_CULL = 4
 
-STAGES = ("preprocess", "inclusive_sum", "host_wait", "duplicate", "sort", "ranges", "tile_order", "render",
-          "load_sums")
+STAGES = ("preprocess", "host_wait", "depth_sort", "inclusive_sum", "duplicate", "tile_sort", "ranges",
+          "tile_order", "render", "load_sums")
 
 EXPORTS = (
     "adr_create_scene", "adr_destroy_scene", "adr_scene_size", "adr_scene_bytes",

@@ -40,7 +40,8 @@ struct DeviceScene {
 struct alignas(16) RenderRecord {
   uint32_t box_x;         // lo | hi << 16: pixel columns that may have alpha >= alpha_low
   uint32_t box_y;         // lo | hi << 16: pixel rows (lo > hi: none)
-  uint32_t pad0, pad1;
+  uint32_t depth_key;     // bits of the fp32 view-space depth
+  uint32_t pad1;
   double x, y;            // projected centre, pixel centres at integers
   float qa, qb, qc, ql;
   float r, g, b;
@@ -91,12 +92,9 @@ struct BlendArgs {
 // Host objects behind the opaque handles
 // ---------------------------------------------------------------------------
 struct SortBuffers {
-  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
-  uint32_t* block_hist = nullptr; // look-back status words, tile counters, digit histograms
-  unsigned long long* err = nullptr; // look-back spin-limit hits (never expected)
   int64_t capacity = 0;
-  int64_t hist_capacity = 0;
 };
 
 }  // namespace adr
@@ -106,25 +104,31 @@ struct adr_scene {
 };
 
 struct adr_workspace {
+  // per Gaussian
   int64_t gauss_capacity = 0;
   adr::RenderRecord* rec = nullptr;
   adr::ExactRecord* exact = nullptr;
   uint2* tile_rect = nullptr;      // (tx_lo | tx_hi << 16, ty_lo | ty_hi << 16)
-  float* depth = nullptr;
   uint32_t* touched = nullptr;
-  uint32_t* offsets = nullptr;     // inclusive sum of touched
+  uint32_t* offsets = nullptr;     // inclusive sum of touched in depth order
+  adr::SortBuffers depth;          // (depth key, id) of every Gaussian, sorted by depth
   uint32_t* scan_partials = nullptr;
   int64_t scan_partials_capacity = 0;
-  adr::SortBuffers sort;
+  // per pair
+  adr::SortBuffers pairs;          // (tile id, Gaussian id), sorted by tile
+  uint32_t* sort_scratch = nullptr;
+  int64_t sort_scratch_capacity = 0;
+  // per tile
   uint32_t* ranges = nullptr;      // 2 * tiles
   int64_t ranges_capacity = 0;
   uint32_t* tile_order = nullptr;  // render order of the tiles, longest lists first
   int64_t tile_order_capacity = 0;
   unsigned long long* wave_sums = nullptr;  // 4 x u64 per render wave (load-sum partials)
   int64_t wave_sums_capacity = 0;
-  unsigned long long* dev_counters = nullptr; // [0] pairs, [1] visible, [2] band, [3] replays, [4] sort spin limit
+  // counters and timing
+  unsigned long long* dev_counters = nullptr;  // [0] pairs, [1] visible, [2] band, [3] replays
   unsigned long long* host_counters = nullptr; // pinned mirror
-  static constexpr int kEvents = 10;
+  static constexpr int kEvents = 11;
   hipEvent_t ev[kEvents] = {};
   bool timing_valid = false;
   hipStream_t last_stream = nullptr;
@@ -149,17 +153,19 @@ hipError_t launch_pack_scene(const adr_scene_desc& desc, const float* means, con
                              hipStream_t stream);
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
                              hipStream_t stream);
-hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
-                                hipStream_t stream);
+hipError_t launch_inclusive_sum(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
+                                uint32_t* partials, hipStream_t stream);
 int64_t inclusive_sum_partials(int64_t n);
-hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* touched, const uint2* tile_rect,
-                            const float* depth, int64_t n, int64_t n_pairs, int32_t tiles_x, uint64_t* keys,
-                            uint32_t* vals, hipStream_t stream);
-hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* result_buffer,
-                             hipStream_t stream);
-int64_t sort_hist_entries(int64_t n_pairs);
-hipError_t launch_tile_ranges(const uint64_t* keys, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint32_t* touched,
+                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
+                            uint32_t* tile_keys, uint32_t* vals, hipStream_t stream);
+hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t* scratch,
+                             int* result_buffer, hipStream_t stream);
+int64_t sort_scratch_entries(int64_t n);
+hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);
+hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, const RenderRecord* rec,
+                               int64_t n_pairs, uint64_t* keys, hipStream_t stream);
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order,
                              hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,

@@ -41,41 +41,44 @@ adr_status grow(T*& p, int64_t& cap, int64_t need, const char* what) {
   return ADR_OK;
 }
 
-adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
-  if (n <= ws->gauss_capacity && ws->rec) return ADR_OK;
-  int64_t cap = ws->gauss_capacity;
-  int64_t c1 = cap, c2 = cap, c3 = cap, c4 = cap, c5 = cap, c6 = cap;
+adr_status ensure_sort_buffers(SortBuffers& sb, int64_t n, const char* what) {
+  if (n <= sb.capacity && sb.keys[0]) return ADR_OK;
+  int64_t c[4] = {sb.capacity, sb.capacity, sb.capacity, sb.capacity};
   adr_status st;
-  if ((st = grow(ws->rec, c1, n, "records")) != ADR_OK) return st;
-  if ((st = grow(ws->exact, c2, n, "exact records")) != ADR_OK) return st;
-  if ((st = grow(ws->tile_rect, c3, n, "tile rects")) != ADR_OK) return st;
-  if ((st = grow(ws->depth, c4, n, "depths")) != ADR_OK) return st;
-  if ((st = grow(ws->touched, c5, n, "tiles_touched")) != ADR_OK) return st;
-  if ((st = grow(ws->offsets, c6, n, "offsets")) != ADR_OK) return st;
-  int64_t m = c1;
-  m = c2 < m ? c2 : m;
-  m = c3 < m ? c3 : m;
-  m = c4 < m ? c4 : m;
-  m = c5 < m ? c5 : m;
-  m = c6 < m ? c6 : m;
-  ws->gauss_capacity = m;
+  if ((st = grow(sb.keys[0], c[0], n, what)) != ADR_OK) return st;
+  if ((st = grow(sb.keys[1], c[1], n, what)) != ADR_OK) return st;
+  if ((st = grow(sb.vals[0], c[2], n, what)) != ADR_OK) return st;
+  if ((st = grow(sb.vals[1], c[3], n, what)) != ADR_OK) return st;
+  int64_t m = c[0];
+  for (int i = 1; i < 4; ++i) m = c[i] < m ? c[i] : m;
+  sb.capacity = m;
+  return ADR_OK;
+}
+
+adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
+  adr_status st;
+  if (n > ws->gauss_capacity || !ws->rec) {
+    int64_t c[4] = {ws->gauss_capacity, ws->gauss_capacity, ws->gauss_capacity, ws->gauss_capacity};
+    int64_t c5 = ws->gauss_capacity;
+    if ((st = grow(ws->rec, c[0], n, "records")) != ADR_OK) return st;
+    if ((st = grow(ws->exact, c[1], n, "exact records")) != ADR_OK) return st;
+    if ((st = grow(ws->tile_rect, c[2], n, "tile rects")) != ADR_OK) return st;
+    if ((st = grow(ws->touched, c[3], n, "tiles_touched")) != ADR_OK) return st;
+    if ((st = grow(ws->offsets, c5, n, "offsets")) != ADR_OK) return st;
+    int64_t m = c5;
+    for (int i = 0; i < 4; ++i) m = c[i] < m ? c[i] : m;
+    ws->gauss_capacity = m;
+  }
+  if ((st = ensure_sort_buffers(ws->depth, n, "depth sort")) != ADR_OK) return st;
+  if ((st = grow(ws->sort_scratch, ws->sort_scratch_capacity, sort_scratch_entries(n), "sort scratch")) != ADR_OK)
+    return st;
   return grow(ws->scan_partials, ws->scan_partials_capacity, inclusive_sum_partials(n) + 1, "scan partials");
 }
 
 adr_status ensure_pairs(adr_workspace* ws, int64_t p) {
-  SortBuffers& sb = ws->sort;
-  if (p > sb.capacity || !sb.keys[0]) {
-    int64_t c0 = sb.capacity, c1 = sb.capacity, c2 = sb.capacity, c3 = sb.capacity;
-    adr_status st;
-    if ((st = grow(sb.keys[0], c0, p, "keys")) != ADR_OK) return st;
-    if ((st = grow(sb.keys[1], c1, p, "keys")) != ADR_OK) return st;
-    if ((st = grow(sb.vals[0], c2, p, "values")) != ADR_OK) return st;
-    if ((st = grow(sb.vals[1], c3, p, "values")) != ADR_OK) return st;
-    sb.capacity = c0 < c1 ? c0 : c1;
-    sb.capacity = c2 < sb.capacity ? c2 : sb.capacity;
-    sb.capacity = c3 < sb.capacity ? c3 : sb.capacity;
-  }
-  return grow(sb.block_hist, sb.hist_capacity, sort_hist_entries(p < 1 ? 1 : p), "sort status");
+  adr_status st;
+  if ((st = ensure_sort_buffers(ws->pairs, p, "pair sort")) != ADR_OK) return st;
+  return grow(ws->sort_scratch, ws->sort_scratch_capacity, sort_scratch_entries(p), "sort scratch");
 }
 
 int bits_for(int64_t v) {
@@ -114,7 +117,6 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
     return ADR_E_OOM;
   }
   std::memset(ws->host_counters, 0, kCounters * sizeof(unsigned long long));
-  ws->sort.err = ws->dev_counters + 4;
   for (int i = 0; i < adr_workspace::kEvents; ++i) {
     if (hipEventCreate(&ws->ev[i]) != hipSuccess) {
       (void)hipGetLastError();
@@ -133,9 +135,10 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
 extern "C" void adr_workspace_destroy(adr_workspace* ws) {
   if (!ws) return;
   (void)hipDeviceSynchronize();
-  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->depth, ws->touched, ws->offsets, ws->scan_partials,
-                  ws->sort.keys[0], ws->sort.keys[1], ws->sort.vals[0], ws->sort.vals[1], ws->sort.block_hist,
-                  ws->ranges, ws->tile_order, ws->wave_sums, ws->dev_counters};
+  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->depth.keys[0],
+                  ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
+                  ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->sort_scratch, ws->ranges,
+                  ws->tile_order, ws->wave_sums, ws->dev_counters};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ws->host_counters) (void)hipHostFree(ws->host_counters);
@@ -254,17 +257,15 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ADR_HIP(launch_fill_u64(ws->dev_counters, 0ull, kCounters, stream));
   ADR_HIP(launch_preprocess(s, ca, cu, ws, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
-  // Stage 2: InclusiveSum
-  ADR_HIP(launch_inclusive_sum(ws->touched, ws->offsets, s.n, ws->scan_partials, stream));
-  if (timing) ADR_HIP(hipEventRecord(ws->ev[2], stream));
   // The pair count sizes everything after this point: one 16-byte readback.
   ADR_HIP(hipMemcpyAsync(ws->host_counters, ws->dev_counters, 2 * sizeof(unsigned long long),
                          hipMemcpyDeviceToHost, stream));
   ADR_HIP(hipStreamSynchronize(stream));
   const unsigned long long n_pairs_u = ws->host_counters[0];
-  if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
-  if (n_pairs_u >= (1ull << 30)) {
-    set_error("adr_render: more than 2^30 Gaussian-tile pairs in one frame");
+  const int64_t n_vis = (int64_t)ws->host_counters[1];
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[2], stream));
+  if (n_pairs_u >= (1ull << 32)) {
+    set_error("adr_render: 2^32 or more Gaussian-tile pairs in one frame");
     out->n_pairs = (int64_t)n_pairs_u;
     return ADR_E_UNSUPPORTED;
   }
@@ -273,29 +274,38 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ws->last_pairs = n_pairs;
   if ((st = ensure_pairs(ws, n_pairs)) != ADR_OK) return st;
 
-  // Stage 3: DuplicateWithKeys
-  ADR_HIP(launch_duplicate(ws->offsets, ws->touched, ws->tile_rect, ws->depth, s.n, n_pairs, ca.tiles_x,
-                           ws->sort.keys[0], ws->sort.vals[0], stream));
+  // Stage 4a: every Gaussian by its 32-bit depth key (ties keep id order);
+  // the visible ones come first.
+  int dsorted = 0;  // which of the two buffers holds the result
+  ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, 32, ws->sort_scratch, &dsorted, stream));
+  const uint32_t* order = ws->depth.vals[dsorted];
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
+  // Stage 2: InclusiveSum of tiles_touched over the Gaussians in depth order
+  ADR_HIP(launch_inclusive_sum(ws->touched, order, ws->offsets, n_vis, ws->scan_partials, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[4], stream));
-  // Stage 4: SortPairs over 32 depth bits + tile-id bits
-  int sorted = 0;
-  const int n_bits = 32 + bits_for(n_tiles);
-  ADR_HIP(launch_sort_pairs(ws->sort, n_pairs, n_bits, &sorted, stream));
-  const uint64_t* keys = ws->sort.keys[sorted];
-  const uint32_t* vals = ws->sort.vals[sorted];
+  // Stage 3: DuplicateWithKeys, in depth order, keyed by tile id
+  ADR_HIP(launch_duplicate(ws->offsets, order, ws->touched, ws->tile_rect, n_vis, n_pairs, ca.tiles_x,
+                           ws->pairs.keys[0], ws->pairs.vals[0], stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[5], stream));
-  // Stage 5: IdentifyTileRanges
-  ADR_HIP(launch_tile_ranges(keys, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
+  // Stage 4b: stable sort by tile id; equal tiles keep the depth order
+  int psorted = 0;
+  ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), ws->sort_scratch, &psorted,
+                            stream));
+  const uint32_t* tiles = ws->pairs.keys[psorted];
+  const uint32_t* vals = ws->pairs.vals[psorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
+  // Stage 5: IdentifyTileRanges
+  ADR_HIP(launch_tile_ranges(tiles, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[7], stream));
   // Stage 6: Render (tile order, blend, load sums)
   ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, stream));
-  if (timing) ADR_HIP(hipEventRecord(ws->ev[7], stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
   ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, ws->wave_sums, n_pairs, s.n, ca,
                         bl, out, ws->dev_counters, stream));
-  if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[9], stream));
   ADR_HIP(launch_load_sums(ws->wave_sums, (int)n_tiles, out->load_sums, stream));
   if (timing) {
-    ADR_HIP(hipEventRecord(ws->ev[9], stream));
+    ADR_HIP(hipEventRecord(ws->ev[10], stream));
     ws->timing_valid = true;
   }
 
@@ -311,8 +321,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
       set_error("adr_render: pair_capacity smaller than the frame's pair count (see n_pairs)");
       return ADR_E_WORKSPACE;
     }
-    if (out->keys && n_pairs > 0)
-      ADR_HIP(hipMemcpyAsync(out->keys, keys, (size_t)n_pairs * sizeof(uint64_t), hipMemcpyDeviceToDevice, stream));
+    if (out->keys) ADR_HIP(launch_compose_keys(tiles, vals, ws->rec, n_pairs, out->keys, stream));
     if (out->values && n_pairs > 0)
       ADR_HIP(hipMemcpyAsync(out->values, vals, (size_t)n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                              stream));

@@ -1,9 +1,11 @@
 // DuplicateWithKeys and IdentifyTileRanges (Sec. 3.2, stages 3 and 5).
 //
 // Pair emission is pair-parallel: lane p finds its Gaussian by binary search
-// in the inclusive offsets, so one Gaussian with a huge rectangle does not
-// serialise a wave, and consecutive lanes write consecutive keys (coalesced).
-// Within a Gaussian the tiles are emitted row-major over its tile rectangle.
+// in the inclusive offsets (taken over the Gaussians in depth order), so one
+// Gaussian with a huge rectangle does not serialise a wave, and consecutive
+// lanes write consecutive pairs (coalesced). Within a Gaussian the tiles are
+// emitted row-major over its tile rectangle. Each pair carries the tile id as
+// its sort key; the depth order is already in the emission order.
 #include "adr_internal.h"
 
 namespace adr {
@@ -11,16 +13,16 @@ namespace adr {
 namespace {
 
 __global__ void __launch_bounds__(256) duplicate_kernel(const uint32_t* __restrict__ offsets,
+                                                        const uint32_t* __restrict__ order,
                                                         const uint32_t* __restrict__ touched,
-                                                        const uint2* __restrict__ tile_rect,
-                                                        const float* __restrict__ depth, int64_t n,
+                                                        const uint2* __restrict__ tile_rect, int64_t n_vis,
                                                         int64_t n_pairs, int32_t tiles_x,
-                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                        uint32_t* __restrict__ tile_keys, uint32_t* __restrict__ vals) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
   const uint32_t pp = (uint32_t)p;
-  // smallest g with offsets[g] > p
-  int64_t lo = 0, hi = n - 1;
+  // smallest r with offsets[r] > p
+  int64_t lo = 0, hi = n_vis - 1;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
     if (offsets[mid] > pp)
@@ -28,27 +30,34 @@ __global__ void __launch_bounds__(256) duplicate_kernel(const uint32_t* __restri
     else
       lo = mid + 1;
   }
-  const int64_t g = lo;
-  const uint32_t k = pp - (offsets[g] - touched[g]);
+  const uint32_t g = order[lo];
+  const uint32_t k = pp - (offsets[lo] - touched[g]);
   const uint2 r = tile_rect[g];
   const uint32_t tx_lo = r.x & 0xffffu, tx_hi = r.x >> 16;
   const uint32_t ty_lo = r.y & 0xffffu;
   const uint32_t w = tx_hi - tx_lo + 1;
-  const uint32_t tx = tx_lo + k % w;
-  const uint32_t ty = ty_lo + k / w;
-  const uint64_t tile = (uint64_t)ty * (uint64_t)tiles_x + tx;
-  keys[p] = (tile << 32) | (uint64_t)__float_as_uint(depth[g]);
-  vals[p] = (uint32_t)g;
+  tile_keys[p] = (ty_lo + k / w) * (uint32_t)tiles_x + tx_lo + k % w;
+  vals[p] = g;
 }
 
-__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint64_t* __restrict__ keys, int64_t n_pairs,
+__global__ void __launch_bounds__(256) tile_ranges_kernel(const uint32_t* __restrict__ tiles, int64_t n_pairs,
                                                           uint32_t* __restrict__ ranges, uint32_t n_tiles) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
-  const uint32_t t = (uint32_t)(keys[p] >> 32);
+  const uint32_t t = tiles[p];
   if (t >= n_tiles) return;  // cannot happen for keys built by duplicate_kernel
-  if (p == 0 || (uint32_t)(keys[p - 1] >> 32) != t) ranges[2 * (int64_t)t] = (uint32_t)p;
-  if (p == n_pairs - 1 || (uint32_t)(keys[p + 1] >> 32) != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(p + 1);
+  if (p == 0 || tiles[p - 1] != t) ranges[2 * (int64_t)t] = (uint32_t)p;
+  if (p == n_pairs - 1 || tiles[p + 1] != t) ranges[2 * (int64_t)t + 1] = (uint32_t)(p + 1);
+}
+
+// The 64-bit keys of the sorted pairs, (tile << 32) | depth bits.
+__global__ void __launch_bounds__(256) compose_keys_kernel(const uint32_t* __restrict__ tiles,
+                                                           const uint32_t* __restrict__ vals,
+                                                           const RenderRecord* __restrict__ rec, int64_t n_pairs,
+                                                           uint64_t* __restrict__ keys) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  keys[p] = ((uint64_t)tiles[p] << 32) | rec[vals[p]].depth_key;
 }
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
@@ -63,21 +72,29 @@ __global__ void fill_u64_kernel(unsigned long long* __restrict__ p, unsigned lon
 
 }  // namespace
 
-hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* touched, const uint2* tile_rect,
-                            const float* depth, int64_t n, int64_t n_pairs, int32_t tiles_x, uint64_t* keys,
-                            uint32_t* vals, hipStream_t stream) {
-  if (n_pairs <= 0) return hipSuccess;
-  duplicate_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(offsets, touched, tile_rect, depth,
-                                                                                n, n_pairs, tiles_x, keys, vals);
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint32_t* touched,
+                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
+                            uint32_t* tile_keys, uint32_t* vals, hipStream_t stream) {
+  if (n_pairs <= 0 || n_vis <= 0) return hipSuccess;
+  duplicate_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(
+      offsets, order, touched, tile_rect, n_vis, n_pairs, tiles_x, tile_keys, vals);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const uint64_t* keys, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
+hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream) {
   hipError_t e = launch_fill_u32(ranges, 0u, 2 * (int64_t)n_tiles, stream);
   if (e != hipSuccess || n_pairs <= 0) return e;
-  tile_ranges_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(keys, n_pairs, ranges,
+  tile_ranges_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(tiles, n_pairs, ranges,
                                                                                   (uint32_t)n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, const RenderRecord* rec,
+                               int64_t n_pairs, uint64_t* keys, hipStream_t stream) {
+  if (n_pairs <= 0) return hipSuccess;
+  compose_keys_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(tiles, vals, rec, n_pairs,
+                                                                                   keys);
   return hipGetLastError();
 }
 

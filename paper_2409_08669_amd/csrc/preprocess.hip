@@ -90,9 +90,11 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
     const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
     const float* __restrict__ planes, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, CullArgs cull,
     RenderRecord* __restrict__ rec, ExactRecord* __restrict__ exact, uint2* __restrict__ tile_rect,
-    float* __restrict__ depth_out, uint32_t* __restrict__ touched_out, unsigned long long* __restrict__ counters) {
+    uint32_t* __restrict__ depth_key, uint32_t* __restrict__ depth_id, uint32_t* __restrict__ touched_out,
+    unsigned long long* __restrict__ counters) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t touched = 0;
+  uint32_t dkey = 0xffffffffu;  // Gaussians without pairs sort after every visible one
   if (g < n) {
     const float4 ga = geo_a[g];
     const double mx = ga.x, my = ga.y, mz = ga.z;
@@ -176,7 +178,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
           const int ty_lo = j_lo / kTile, ty_hi = j_hi / kTile;
           touched = (uint32_t)(tx_hi - tx_lo + 1) * (uint32_t)(ty_hi - ty_lo + 1);
           tile_rect[g] = make_uint2(pack16(tx_lo, tx_hi), pack16(ty_lo, ty_hi));
-          depth_out[g] = (float)pz;
+          // view-space depth rounded to fp32; its bits order like the depths (z > 0)
+          dkey = __float_as_uint((float)pz);
           // Render-side cull box. The blend stage skips a Gaussian for an 8 x 8
           // quadrant that this box misses. In the culling modes it is the
           // mode's extent without the r_o cap (Eq. 7 square, or Eq. 10 box),
@@ -208,7 +211,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
           rr.b = cbl;
           rr.box_x = pack16(bx_lo, bx_hi);
           rr.box_y = pack16(by_lo, by_hi);
-          rr.pad0 = rr.pad1 = rr.pad2 = 0u;
+          rr.depth_key = dkey;
+          rr.pad1 = rr.pad2 = 0u;
           rec[g] = rr;
           ExactRecord er;
           er.ca = ca;
@@ -220,6 +224,8 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
       }
     }
     touched_out[g] = touched;
+    depth_key[g] = dkey;
+    depth_id[g] = (uint32_t)g;
   }
   // Pair total (u64, exact) and visible count for the host.
   __shared__ unsigned long long part[2][4];
@@ -263,8 +269,8 @@ hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const Cul
   static const ShConsts shc = make_sh_consts();
   dim3 grid((unsigned)((s.n + 255) / 256));
   preprocess_kernel<<<grid, 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc, cam, cull,
-                                              ws->rec, ws->exact, ws->tile_rect, ws->depth, ws->touched,
-                                              ws->dev_counters);
+                                              ws->rec, ws->exact, ws->tile_rect, ws->depth.keys[0],
+                                              ws->depth.vals[0], ws->touched, ws->dev_counters);
   return hipGetLastError();
 }
 

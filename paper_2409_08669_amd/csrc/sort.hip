@@ -1,16 +1,19 @@
-// SortPairs (Sec. 3.2, stage 4): stable LSD radix sort of (u64 key, u32 id)
-// pairs over the key bits that can be non-zero (32 depth bits plus the tile
-// id bits), 8 bits per pass.
+// SortPairs (Sec. 3.2, stage 4) as two stable LSD radix sorts.
 //
-// One histogram launch reads the keys once and counts the digits of every
-// pass. Each pass is reduce-then-scan: per-workgroup digit counts, one
-// workgroup per digit scans them into scatter offsets, and a downsweep ranks
-// 4096 keys per workgroup in LDS and scatters. A decoupled look-back would
-// save the count read, but across the eight XCDs its serial chain of
-// device-coherent loads cost ~0.5 ms per pass; every step here is parallel.
-// Ranking is stable and uses wave64 ballots: the lanes of a row that share a
-// digit are found with eight ballots, one per digit bit, and counted with
-// popcounts, so no LDS atomics decide an order.
+// Sorting the Gaussian-tile pairs by the 64-bit key (tile << 32 | depth bits)
+// is done in two steps that give the same order: the visible Gaussians are
+// sorted once by their 32-bit depth key (ties keep id order), their pairs are
+// then emitted in that order, and a stable sort on the tile id alone (13 bits
+// at 1080p) groups them by tile without disturbing the depth order. Each pair
+// is moved in two passes instead of the five or six its 38-47 key bits need.
+//
+// Each pass is reduce-then-scan: per-workgroup digit counts, one workgroup
+// per digit scans them into scatter offsets, and a downsweep ranks 4096 keys
+// per workgroup in LDS and scatters them. Ranking is stable and uses wave64
+// ballots: the lanes of a row that share a digit are found with eight
+// ballots, one per digit bit, and counted with popcounts, so no atomics decide
+// an order. (A single-launch decoupled look-back was tried first; its chain of
+// device-coherent loads across the eight XCDs cost ~0.5 ms per pass.)
 #include "adr_internal.h"
 
 namespace adr {
@@ -21,7 +24,7 @@ constexpr int kThreads = 256;
 constexpr int kItems = 16;
 constexpr int kTileKeys = kThreads * kItems;  // 4096 keys per workgroup
 constexpr int kRadix = 256;
-constexpr int kMaxPasses = 8;
+constexpr int kMaxPasses = 4;
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
 #pragma unroll
@@ -43,15 +46,16 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem4)
   return s + before - v;
 }
 
-__global__ void __launch_bounds__(kThreads) digit_histogram_kernel(const uint64_t* __restrict__ keys, int64_t n,
+// Digit counts of every pass in one read of the keys.
+__global__ void __launch_bounds__(kThreads) digit_histogram_kernel(const uint32_t* __restrict__ keys, int64_t n,
                                                                    int n_pass, uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[kMaxPasses][kRadix];
   for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kThreads) (&h[0][0])[i] = 0u;
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
-    const uint64_t k = keys[i];
-    for (int p = 0; p < n_pass; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 0xff], 1u);
+    const uint32_t k = keys[i];
+    for (int p = 0; p < n_pass; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 0xffu], 1u);
   }
   __syncthreads();
   for (int p = 0; p < n_pass; ++p) {
@@ -61,7 +65,7 @@ __global__ void __launch_bounds__(kThreads) digit_histogram_kernel(const uint64_
 }
 
 // Per-workgroup digit counts of one pass: counts[d * nb + b].
-__global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint64_t* __restrict__ kin, int64_t n, int shift,
+__global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __restrict__ kin, int64_t n, int shift,
                                                            uint32_t* __restrict__ counts, int64_t nb) {
   __shared__ uint32_t wh[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -71,7 +75,7 @@ __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint64_t* __res
 #pragma unroll 4
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
-    if (idx < n) atomicAdd(&wh[wid][(uint32_t)(kin[idx] >> shift) & 0xffu], 1u);
+    if (idx < n) atomicAdd(&wh[wid][(kin[idx] >> shift) & 0xffu], 1u);
   }
   __syncthreads();
   counts[(int64_t)tid * nb + blockIdx.x] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
@@ -82,10 +86,10 @@ __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint64_t* __res
 __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __restrict__ counts, int64_t nb,
                                                                  const uint32_t* __restrict__ hist) {
   __shared__ uint32_t scan_tmp[4];
-  const int d = blockIdx.x;
-  // digit base: exclusive prefix of the global histogram at d
-  const uint32_t base = block_excl_scan(hist[threadIdx.x], scan_tmp);
   __shared__ uint32_t s_base;
+  __shared__ uint32_t s_last;
+  const int d = blockIdx.x;
+  const uint32_t base = block_excl_scan(hist[threadIdx.x], scan_tmp);
   if ((int)threadIdx.x == d) s_base = base;
   __syncthreads();
   uint32_t carry = s_base;
@@ -94,7 +98,6 @@ __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __res
     const int64_t b = b0 + threadIdx.x;
     const uint32_t v = b < nb ? row[b] : 0u;
     const uint32_t ex = block_excl_scan(v, scan_tmp);
-    __shared__ uint32_t s_last;
     if (threadIdx.x == kThreads - 1) s_last = ex + v;
     __syncthreads();
     if (b < nb) row[b] = carry + ex;
@@ -103,14 +106,14 @@ __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __res
   }
 }
 
-// Stable rank of the workgroup's 4096 keys and scatter to the offsets of
-// the pass.
-__global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint64_t* __restrict__ kin,
+// Stable rank of the workgroup's 4096 keys and scatter to the offsets of the
+// pass.
+__global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
-                                                             uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n, int shift, const uint32_t* __restrict__ offsets,
                                                              int64_t nb) {
-  __shared__ uint64_t skeys[kTileKeys];
+  __shared__ uint32_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
   __shared__ uint32_t wcnt[4][kRadix];
   __shared__ uint32_t blk_start[kRadix];
@@ -125,21 +128,21 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint64_t* __r
   const int64_t wave_base = (int64_t)bid * kTileKeys + (int64_t)wid * (kItems * 64);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  uint64_t k[kItems];
+  uint32_t k[kItems];
   uint32_t v[kItems];
   uint32_t rank[kItems];
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
     const bool valid = idx < n;
-    k[r] = valid ? kin[idx] : ~0ull;
+    k[r] = valid ? kin[idx] : 0xffffffffu;
     v[r] = valid ? vin[idx] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
     const bool valid = idx < n;
-    const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
+    const uint32_t d = (k[r] >> shift) & 0xffu;
     // lanes of this row holding the same digit, from one ballot per digit bit
     uint64_t m = __ballot(valid);
 #pragma unroll
@@ -171,7 +174,7 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint64_t* __r
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
     if (idx < n) {
-      const uint32_t dd = (uint32_t)(k[r] >> shift) & 0xffu;
+      const uint32_t dd = (k[r] >> shift) & 0xffu;
       const uint32_t pos = blk_start[dd] + wcnt[wid][dd] + rank[r];
       skeys[pos] = k[r];
       svals[pos] = v[r];
@@ -181,8 +184,8 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint64_t* __r
   const int64_t left = n - (int64_t)bid * kTileKeys;
   const int count = left < kTileKeys ? (int)left : kTileKeys;
   for (int i = tid; i < count; i += kThreads) {
-    const uint64_t key = skeys[i];
-    const uint32_t dd = (uint32_t)(key >> shift) & 0xffu;
+    const uint32_t key = skeys[i];
+    const uint32_t dd = (key >> shift) & 0xffu;
     const uint32_t o = glob_base[dd] + (uint32_t)i - blk_start[dd];
     if (o < (uint64_t)n) {  // always true for a correct ranking; keeps a fault impossible
       kout[o] = key;
@@ -193,33 +196,33 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint64_t* __r
 
 }  // namespace
 
-int64_t sort_hist_entries(int64_t n_pairs) {
-  const int64_t nb = (n_pairs + kTileKeys - 1) / kTileKeys;
+int64_t sort_scratch_entries(int64_t n) {
+  const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
   // digit counts / offsets [256][nb], then the global histograms [kMaxPasses][256]
-  return (int64_t)kRadix * nb + kMaxPasses * kRadix;
+  return (int64_t)kRadix * (nb > 0 ? nb : 1) + kMaxPasses * kRadix;
 }
 
-hipError_t launch_sort_pairs(SortBuffers& sb, int64_t n_pairs, int n_bits, int* result_buffer,
-                             hipStream_t stream) {
+hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t* scratch,
+                             int* result_buffer, hipStream_t stream) {
   *result_buffer = 0;
-  if (n_pairs <= 1) return hipSuccess;
+  if (n <= 1 || n_bits <= 0) return hipSuccess;
   const int n_pass = (n_bits + 7) / 8;
   if (n_pass > kMaxPasses) return hipErrorInvalidValue;
-  const int64_t nb = (n_pairs + kTileKeys - 1) / kTileKeys;
-  uint32_t* counts = sb.block_hist;
+  const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
+  uint32_t* counts = scratch;
   uint32_t* hist = counts + (int64_t)kRadix * nb;
   hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kRadix, stream);
   if (e != hipSuccess) return e;
-  int64_t hist_blocks = (n_pairs + kThreads * 16 - 1) / (kThreads * 16);
+  int64_t hist_blocks = (n + kThreads * 16 - 1) / (kThreads * 16);
   if (hist_blocks > 2048) hist_blocks = 2048;
-  digit_histogram_kernel<<<dim3((unsigned)hist_blocks), kThreads, 0, stream>>>(sb.keys[0], n_pairs, n_pass, hist);
+  digit_histogram_kernel<<<dim3((unsigned)hist_blocks), kThreads, 0, stream>>>(keys[0], n, n_pass, hist);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int p = 0; p < n_pass; ++p) {
-    upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(sb.keys[cur], n_pairs, 8 * p, counts, nb);
+    upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, counts, nb);
     digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, hist + p * kRadix);
-    downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(sb.keys[cur], sb.vals[cur], sb.keys[cur ^ 1],
-                                                                    sb.vals[cur ^ 1], n_pairs, 8 * p, counts, nb);
+    downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                                    vals[cur ^ 1], n, 8 * p, counts, nb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
