@@ -118,21 +118,28 @@ def main():
     results = {}
     images = {}
     for name, (mode, extra) in modes.items():
-        params = P.RenderParams(cull=mode, flags=P.ADR_FLAG_TIMING | extra)
+        params = P.RenderParams(cull=mode, flags=extra)
+        timed = P.RenderParams(cull=mode, flags=P.ADR_FLAG_TIMING | extra)
         log(f"mode {name}: warmup {args.warmup}")
         for _ in range(args.warmup):
             P.render(sg, cam, params, ws, **out)
         torch.cuda.synchronize()
-        stage_sum = {s: 0.0 for s in STAGES}
+        # Throughput: frames back to back, no per-stage events (each event
+        # record costs a few microseconds of GPU idle time).
         log(f"mode {name}: timing {args.steps} frames")
         t0 = time.perf_counter()
         for _ in range(args.steps):
             n_pairs = P.render(sg, cam, params, ws, **out)
-            st = ws.stage_times()
-            for k, v in st.items():
-                stage_sum[k] += v
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # Stage durations: the same frames again with HIP events around every
+        # stage, recorded on the library's stream, read after each frame.
+        stage_sum = {s: 0.0 for s in STAGES}
+        for _ in range(args.steps):
+            P.render(sg, cam, timed, ws, **out)
+            for k, v in ws.stage_times().items():
+                stage_sum[k] += v
+        torch.cuda.synchronize()
         counters = ws.counters()
         sums = out["load_sums"].cpu().numpy()
         mean_b, std_b = P.load_stats_from_sums(sums[0:2], w * h)

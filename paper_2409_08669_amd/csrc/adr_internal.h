@@ -123,11 +123,17 @@ struct adr_workspace {
   int64_t ranges_capacity = 0;
   uint32_t* tile_order = nullptr;  // render order of the tiles, longest lists first
   int64_t tile_order_capacity = 0;
-  unsigned long long* wave_sums = nullptr;  // 4 x u64 per render wave (load-sum partials)
+  // per frame: counters and the two sort histograms, zeroed (with the tile
+  // ranges and the caller's load sums) by one kernel at the start of the frame
+  unsigned long long* dev_counters = nullptr;  // kCounterSlots u64, see below
+  uint32_t* hists = nullptr;                   // 2 x kHistWords: depth sort, tile sort
+  unsigned long long* wave_sums = nullptr;     // 4 x u64 per render wave (load-sum partials)
   int64_t wave_sums_capacity = 0;
-  // counters and timing
-  unsigned long long* dev_counters = nullptr;  // [0] pairs, [1] visible, [2] band, [3] replays
-  unsigned long long* host_counters = nullptr; // pinned mirror
+  unsigned long long* host_counters = nullptr; // pinned copy for adr_workspace_counters
+  // mapped pinned memory the Preprocess kernel writes the pair count into
+  unsigned long long* notify_host = nullptr;
+  unsigned long long* notify_dev = nullptr;
+  unsigned long long frame_seq = 0;
   static constexpr int kEvents = 11;
   hipEvent_t ev[kEvents] = {};
   bool timing_valid = false;
@@ -136,6 +142,14 @@ struct adr_workspace {
 };
 
 namespace adr {
+
+// dev_counters slots
+constexpr int kCntPairs = 0;       // sum of tiles_touched (u64)
+constexpr int kCntVisible = 1;     // Gaussians with tiles_touched > 0
+constexpr int kCntBand = 2;        // FP64 re-decisions near alpha_low
+constexpr int kCntReplay = 3;      // FP64 transmittance replays near t_min
+constexpr int kCounterSlots = 8;
+constexpr int kHistWords = 4 * 256;  // digit histograms of up to four 8-bit passes
 
 // Thread-local error message for adr_last_error.
 void set_error(const std::string& msg);
@@ -151,6 +165,7 @@ adr_status hip_fail(hipError_t e, const char* what);
 hipError_t launch_pack_scene(const adr_scene_desc& desc, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh, DeviceScene& d,
                              hipStream_t stream);
+hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_sums, hipStream_t stream);
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
                              hipStream_t stream);
 hipError_t launch_inclusive_sum(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
@@ -160,7 +175,7 @@ hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, cons
                             const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
                             uint32_t* tile_keys, uint32_t* vals, hipStream_t stream);
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t* scratch,
-                             int* result_buffer, hipStream_t stream);
+                             uint32_t* hist, int* result_buffer, hipStream_t stream);
 int64_t sort_scratch_entries(int64_t n);
 hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);
@@ -169,10 +184,10 @@ hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, cons
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order,
                              hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
-                         const uint32_t* ranges, const uint32_t* order, void* wave_sums, int64_t n_pairs,
-                         int64_t n_gauss, const CamArgs& cam, const BlendArgs& blend, adr_frame* out,
-                         unsigned long long* counters, hipStream_t stream);
-hipError_t launch_load_sums(const void* wave_sums, int n_tiles, uint64_t* load_sums, hipStream_t stream);
+                         const uint32_t* ranges, const uint32_t* order, int64_t n_pairs, int64_t n_gauss,
+                         const CamArgs& cam, const BlendArgs& blend, adr_frame* out, adr_workspace* ws,
+                         hipStream_t stream);
+hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 

@@ -1,5 +1,7 @@
 // C ABI: workspace management and the per-frame orchestration of the six
 // stages of Sec. 3.2 on the caller's stream.
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -11,7 +13,6 @@ namespace adr {
 
 namespace {
 thread_local std::string g_error;
-constexpr int kCounters = 8;
 }  // namespace
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -92,6 +93,17 @@ int bits_for(int64_t v) {
 
 using namespace adr;
 
+static void free_workspace_buffers(adr_workspace* ws) {
+  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->depth.keys[0],
+                  ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
+                  ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->sort_scratch, ws->ranges,
+                  ws->tile_order, ws->wave_sums, ws->dev_counters, ws->hists};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (ws->host_counters) (void)hipHostFree(ws->host_counters);
+  if (ws->notify_host) (void)hipHostFree(ws->notify_host);
+}
+
 extern "C" const char* adr_last_error(void) { return g_error.c_str(); }
 
 extern "C" const char* adr_version(void) { return "adr-gfx950 0.1"; }
@@ -107,23 +119,30 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
     set_error("adr_workspace_create: host allocation failed");
     return ADR_E_OOM;
   }
-  if (hipMalloc(&ws->dev_counters, kCounters * sizeof(unsigned long long)) != hipSuccess ||
-      hipHostMalloc(&ws->host_counters, kCounters * sizeof(unsigned long long), hipHostMallocDefault) !=
-          hipSuccess) {
+  bool ok = hipMalloc(&ws->dev_counters, kCounterSlots * sizeof(unsigned long long)) == hipSuccess &&
+            hipMalloc(&ws->hists, 2 * kHistWords * sizeof(uint32_t)) == hipSuccess &&
+            hipHostMalloc(&ws->host_counters, kCounterSlots * sizeof(unsigned long long), hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc(&ws->notify_host, 4 * sizeof(unsigned long long),
+                          hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
+  if (ok) {
+    std::memset(ws->host_counters, 0, kCounterSlots * sizeof(unsigned long long));
+    std::memset(ws->notify_host, 0, 4 * sizeof(unsigned long long));
+    ok = hipHostGetDevicePointer((void**)&ws->notify_dev, ws->notify_host, 0) == hipSuccess;
+  }
+  if (!ok) {
     (void)hipGetLastError();
-    if (ws->dev_counters) (void)hipFree(ws->dev_counters);
+    free_workspace_buffers(ws);
     delete ws;
     set_error("adr_workspace_create: allocation failed");
     return ADR_E_OOM;
   }
-  std::memset(ws->host_counters, 0, kCounters * sizeof(unsigned long long));
   for (int i = 0; i < adr_workspace::kEvents; ++i) {
     if (hipEventCreate(&ws->ev[i]) != hipSuccess) {
       (void)hipGetLastError();
       set_error("adr_workspace_create: hipEventCreate failed");
       for (int k = 0; k < i; ++k) (void)hipEventDestroy(ws->ev[k]);
-      (void)hipFree(ws->dev_counters);
-      (void)hipHostFree(ws->host_counters);
+      free_workspace_buffers(ws);
       delete ws;
       return ADR_E_HIP;
     }
@@ -135,13 +154,7 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
 extern "C" void adr_workspace_destroy(adr_workspace* ws) {
   if (!ws) return;
   (void)hipDeviceSynchronize();
-  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->depth.keys[0],
-                  ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
-                  ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->sort_scratch, ws->ranges,
-                  ws->tile_order, ws->wave_sums, ws->dev_counters};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
-  if (ws->host_counters) (void)hipHostFree(ws->host_counters);
+  free_workspace_buffers(ws);
   for (auto& e : ws->ev)
     if (e) (void)hipEventDestroy(e);
   delete ws;
@@ -253,16 +266,34 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ws->last_stream = stream;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[0], stream));
 
+  // Clear the frame's counters, histograms, load partials and tile ranges.
+  ADR_HIP(launch_frame_init(ws, n_tiles, out->load_sums, stream));
   // Stage 1: Preprocess (+ pair total and visible count)
-  ADR_HIP(launch_fill_u64(ws->dev_counters, 0ull, kCounters, stream));
+  ws->frame_seq += 1;
   ADR_HIP(launch_preprocess(s, ca, cu, ws, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
-  // The pair count sizes everything after this point: one 16-byte readback.
-  ADR_HIP(hipMemcpyAsync(ws->host_counters, ws->dev_counters, 2 * sizeof(unsigned long long),
-                         hipMemcpyDeviceToHost, stream));
-  ADR_HIP(hipStreamSynchronize(stream));
-  const unsigned long long n_pairs_u = ws->host_counters[0];
-  const int64_t n_vis = (int64_t)ws->host_counters[1];
+  // The pair count sizes everything after this point. The last Preprocess
+  // workgroup writes it to mapped host memory; wait for this frame's number.
+  unsigned long long n_pairs_u = 0, n_vis_u = 0;
+  if (s.n > 0) {
+    volatile unsigned long long* nf = ws->notify_host;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (nf[2] != ws->frame_seq) {
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
+        // slow frame or a failed launch: fall back to the stream's status
+        ADR_HIP(hipStreamSynchronize(stream));
+        if (nf[2] != ws->frame_seq) {
+          set_error("adr_render: Preprocess did not report the pair count");
+          return ADR_E_HIP;
+        }
+        break;
+      }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    n_pairs_u = nf[0];
+    n_vis_u = nf[1];
+  }
+  const int64_t n_vis = (int64_t)n_vis_u;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[2], stream));
   if (n_pairs_u >= (1ull << 32)) {
     set_error("adr_render: 2^32 or more Gaussian-tile pairs in one frame");
@@ -277,7 +308,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   // Stage 4a: every Gaussian by its 32-bit depth key (ties keep id order);
   // the visible ones come first.
   int dsorted = 0;  // which of the two buffers holds the result
-  ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, 32, ws->sort_scratch, &dsorted, stream));
+  ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, 32, ws->sort_scratch, ws->hists, &dsorted,
+                            stream));
   const uint32_t* order = ws->depth.vals[dsorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
   // Stage 2: InclusiveSum of tiles_touched over the Gaussians in depth order
@@ -289,8 +321,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if (timing) ADR_HIP(hipEventRecord(ws->ev[5], stream));
   // Stage 4b: stable sort by tile id; equal tiles keep the depth order
   int psorted = 0;
-  ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), ws->sort_scratch, &psorted,
-                            stream));
+  ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), ws->sort_scratch,
+                            ws->hists + kHistWords, &psorted, stream));
   const uint32_t* tiles = ws->pairs.keys[psorted];
   const uint32_t* vals = ws->pairs.vals[psorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
@@ -300,10 +332,10 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   // Stage 6: Render (tile order, blend, load sums)
   ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
-  ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, ws->wave_sums, n_pairs, s.n, ca,
-                        bl, out, ws->dev_counters, stream));
+  ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, n_pairs, s.n, ca, bl, out, ws,
+                        stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[9], stream));
-  ADR_HIP(launch_load_sums(ws->wave_sums, (int)n_tiles, out->load_sums, stream));
+  ADR_HIP(launch_load_sums(ws, (int)n_tiles, out->load_sums, stream));
   if (timing) {
     ADR_HIP(hipEventRecord(ws->ev[10], stream));
     ws->timing_valid = true;
@@ -356,12 +388,13 @@ extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32
 extern "C" int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n) {
   if (!ws || !out || n <= 0) return 0;
   if (hipStreamSynchronize(ws->last_stream) != hipSuccess ||
-      hipMemcpy(ws->host_counters, ws->dev_counters, kCounters * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
-          hipSuccess) {
+      hipMemcpy(ws->host_counters, ws->dev_counters, kCounterSlots * sizeof(unsigned long long),
+                hipMemcpyDeviceToHost) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
+  const int idx[5] = {kCntPairs, kCntVisible, kCntBand, kCntReplay, -1};
   int32_t k = 0;
-  for (; k < 5 && k < n; ++k) out[k] = (int64_t)ws->host_counters[k];
+  for (; k < 5 && k < n; ++k) out[k] = idx[k] >= 0 ? (int64_t)ws->host_counters[idx[k]] : 0;
   return k;
 }

@@ -60,6 +60,19 @@ __global__ void __launch_bounds__(256) compose_keys_kernel(const uint32_t* __res
   keys[p] = ((uint64_t)tiles[p] << 32) | rec[vals[p]].depth_key;
 }
 
+// Clears everything a frame accumulates into: counters, sort histograms,
+// the caller's load sums and the tile ranges (empty tiles keep (0, 0)).
+__global__ void __launch_bounds__(256) frame_init_kernel(unsigned long long* __restrict__ counters,
+                                                         uint32_t* __restrict__ hists,
+                                                         unsigned long long* __restrict__ load_sums,
+                                                         uint32_t* __restrict__ ranges, int64_t n_ranges) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kCounterSlots) counters[i] = 0ull;
+  if (i < 2 * kHistWords) hists[i] = 0u;
+  if (load_sums && i < 4) load_sums[i] = 0ull;
+  if (i < n_ranges) ranges[i] = 0u;
+}
+
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -81,10 +94,10 @@ hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, cons
   return hipGetLastError();
 }
 
+// ranges must be zero on entry (the frame-init kernel clears them)
 hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream) {
-  hipError_t e = launch_fill_u32(ranges, 0u, 2 * (int64_t)n_tiles, stream);
-  if (e != hipSuccess || n_pairs <= 0) return e;
+  if (n_pairs <= 0) return hipSuccess;
   tile_ranges_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(tiles, n_pairs, ranges,
                                                                                   (uint32_t)n_tiles);
   return hipGetLastError();
@@ -95,6 +108,14 @@ hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, cons
   if (n_pairs <= 0) return hipSuccess;
   compose_keys_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(tiles, vals, rec, n_pairs,
                                                                                    keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_sums, hipStream_t stream) {
+  int64_t n = 2 * n_tiles;
+  if (n < 2 * kHistWords) n = 2 * kHistWords;
+  frame_init_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, stream>>>(
+      ws->dev_counters, ws->hists, (unsigned long long*)load_sums, ws->ranges, 2 * n_tiles);
   return hipGetLastError();
 }
 

@@ -17,26 +17,32 @@ struct ShConsts {
   float k[16];
 };
 
-__device__ __forceinline__ void sh_colour(const float* __restrict__ planes, int64_t n, int64_t g, int n_coeff,
-                                          const ShConsts& kc, float x, float y, float z, float& r, float& gr,
-                                          float& b) {
+// Colour from K = (d+1)^2 SH coefficients. All 3K loads are issued before
+// any arithmetic (one memory round trip per Gaussian).
+template <int K>
+__device__ __forceinline__ void sh_colour_k(const float* __restrict__ planes, int64_t n, int64_t g,
+                                            const ShConsts& kc, float x, float y, float z, float& r, float& gr,
+                                            float& b) {
+  float coef[3 * K];
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) coef[i] = planes[(int64_t)i * n + g];
   // Polynomial parts P_l^|m|(cos th) cos(m ph) / sin(|m| ph) on the unit
   // sphere, Condon-Shortley phase included; index l*l + l + m.
   float basis[16];
   basis[0] = 1.f;
-  if (n_coeff > 1) {
+  if (K > 1) {
     basis[1] = -y;
     basis[2] = z;
     basis[3] = -x;
   }
-  if (n_coeff > 4) {
+  if (K > 4) {
     const float xx = x * x, yy = y * y, zz = z * z;
     basis[4] = 6.f * x * y;
     basis[5] = -3.f * z * y;
     basis[6] = 0.5f * (3.f * zz - 1.f);
     basis[7] = -3.f * z * x;
     basis[8] = 3.f * (xx - yy);
-    if (n_coeff > 9) {
+    if (K > 9) {
       const float t = -1.5f * (5.f * zz - 1.f);
       basis[9] = -15.f * (3.f * xx * y - yy * y);
       basis[10] = 30.f * x * y * z;
@@ -48,14 +54,26 @@ __device__ __forceinline__ void sh_colour(const float* __restrict__ planes, int6
     }
   }
   float acc[3] = {0.f, 0.f, 0.f};
-  for (int k = 0; k < n_coeff; ++k) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     const float w = kc.k[k] * basis[k];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = fmaf(w, planes[(int64_t)(3 * k + c) * n + g], acc[c]);
+    for (int c = 0; c < 3; ++c) acc[c] = fmaf(w, coef[3 * k + c], acc[c]);
   }
   r = fmaxf(acc[0] + 0.5f, 0.f);
   gr = fmaxf(acc[1] + 0.5f, 0.f);
   b = fmaxf(acc[2] + 0.5f, 0.f);
+}
+
+__device__ __forceinline__ void sh_colour(const float* __restrict__ planes, int64_t n, int64_t g, int n_coeff,
+                                          const ShConsts& kc, float x, float y, float z, float& r, float& gr,
+                                          float& b) {
+  switch (n_coeff) {
+    case 1: sh_colour_k<1>(planes, n, g, kc, x, y, z, r, gr, b); break;
+    case 4: sh_colour_k<4>(planes, n, g, kc, x, y, z, r, gr, b); break;
+    case 9: sh_colour_k<9>(planes, n, g, kc, x, y, z, r, gr, b); break;
+    default: sh_colour_k<16>(planes, n, g, kc, x, y, z, r, gr, b); break;
+  }
 }
 
 __device__ __forceinline__ uint32_t pack16(int lo, int hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
@@ -96,14 +114,15 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
   uint32_t touched = 0;
   uint32_t dkey = 0xffffffffu;  // Gaussians without pairs sort after every visible one
   if (g < n) {
+    // all three geometry loads up front: one round trip
     const float4 ga = geo_a[g];
+    const float4 gb = geo_b[g];
+    const float4 gq = geo_q[g];
     const double mx = ga.x, my = ga.y, mz = ga.z;
     const double px = cam.r[0] * mx + cam.r[1] * my + cam.r[2] * mz + cam.t[0];
     const double py = cam.r[3] * mx + cam.r[4] * my + cam.r[5] * mz + cam.t[1];
     const double pz = cam.r[6] * mx + cam.r[7] * my + cam.r[8] * mz + cam.t[2];
     if (pz > cam.near_z) {
-      const float4 gb = geo_b[g];
-      const float4 gq = geo_q[g];
       // Sigma = R S S^T R^T (Sec. 3.1)
       const double s0 = exp((double)gb.x), s1 = exp((double)gb.y), s2 = exp((double)gb.z);
       double qw = gq.x, qx = gq.y, qy = gq.z, qz = gq.w;
@@ -240,8 +259,20 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
   if (threadIdx.x == 0) {
     const unsigned long long st = part[0][0] + part[0][1] + part[0][2] + part[0][3];
     const unsigned long long sv = part[1][0] + part[1][1] + part[1][2] + part[1][3];
-    if (st) atomicAdd(&counters[0], st);
-    if (sv) atomicAdd(&counters[1], sv);
+    if (st) atomicAdd(&counters[kCntPairs], st);
+    if (sv) atomicAdd(&counters[kCntVisible], sv);
+  }
+}
+
+// Runs after Preprocess on the same stream (the kernel boundary makes every
+// workgroup's counts visible) and hands the pair and visible counts to the
+// host through mapped pinned memory, then publishes the frame's number.
+__global__ void notify_host_kernel(const unsigned long long* __restrict__ counters,
+                                   unsigned long long* __restrict__ notify, unsigned long long seq) {
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&notify[0], counters[kCntPairs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&notify[1], counters[kCntVisible], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&notify[2], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -271,6 +302,7 @@ hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const Cul
   preprocess_kernel<<<grid, 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc, cam, cull,
                                               ws->rec, ws->exact, ws->tile_rect, ws->depth.keys[0],
                                               ws->depth.vals[0], ws->touched, ws->dev_counters);
+  notify_host_kernel<<<1, 64, 0, stream>>>(ws->dev_counters, ws->notify_dev, ws->frame_seq);
   return hipGetLastError();
 }
 

@@ -3,15 +3,16 @@
 // load-balancing cap.
 //
 // Layout: one 256-lane workgroup per 16 x 16 tile; each wave64 owns an 8 x 8
-// quadrant and walks the tile's depth-sorted list on its own, so a quadrant
-// whose pixels are all saturated stops without waiting for the others. Per
-// batch of 64 list entries every lane loads one id and that Gaussian's
-// alpha_low box (8 bytes); a ballot marks the entries whose box meets the
-// quadrant, and only those lanes load the rest of the record into the wave's
-// LDS slots, compacted by their rank in the ballot. The wave then evaluates
-// the compacted entries in list order, reading each with broadcast LDS loads.
-// An entry outside the box has alpha < alpha_low at every pixel of the
-// quadrant, so skipping it changes nothing.
+// quadrant, split into four 4 x 4 sub-blocks of 16 lanes, and walks the
+// tile's depth-sorted list on its own. Per batch of 64 list entries every
+// lane loads one id and that Gaussian's cull box (8 bytes) and tests it
+// against the four sub-blocks; the record of every entry that meets one is
+// staged in LDS, and each sub-block gets the list of its own entries
+// (compacted with ballots, in list order). The wave then steps through the
+// four lists together: on each step the 16 lanes of a sub-block evaluate that
+// sub-block's next Gaussian. An entry whose box misses a sub-block has
+// alpha < alpha_low at all its pixels, so skipping it changes nothing; a
+// Gaussian is evaluated only by the lanes whose pixels it can reach.
 //
 // Precision: the record centre is made quadrant-relative in FP64 before the
 // FP32 evaluation. The skip decision alpha < alpha_low is re-taken in FP64
@@ -31,6 +32,8 @@ struct alignas(16) Staged {
   float4 b;  // qc, ql, r, g
   float4 c;  // b, gid bits, list index bits, 0
 };
+
+constexpr int kSub = 4;  // 4 x 4 pixel sub-blocks, 16 lanes each
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
@@ -140,7 +143,8 @@ __global__ void __launch_bounds__(256) render_kernel(
     CamArgs cam, BlendArgs bl, int n_tiles, float* __restrict__ image, float* __restrict__ final_t,
     uint32_t* __restrict__ l_iter, uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums,
     unsigned long long* __restrict__ counters) {
-  __shared__ Staged stage[4][64];
+  __shared__ Staged stage[4][65];      // slot 64: a null record for lanes past their list's end
+  __shared__ uint8_t lists[4][4][64];  // per wave, per sub-block: staged slots in list order
   const int tile = (int)min(order[blockIdx.x], (uint32_t)(n_tiles - 1));
   const int W = cam.width, H = cam.height;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -148,15 +152,24 @@ __global__ void __launch_bounds__(256) render_kernel(
   const int qx0 = tx * kTile + (wid & 1) * kQuad;
   const int qy0 = ty * kTile + (wid >> 1) * kQuad;
   if (qx0 >= W || qy0 >= H) {  // quadrant entirely outside the image (wave-uniform)
-    if (wave_sums && lane == 0) wave_sums[4 * tile + wid] = make_ulonglong4(0ull, 0ull, 0ull, 0ull);
+    if (wave_sums && lane == 0) wave_sums[4 * blockIdx.x + wid] = make_ulonglong4(0ull, 0ull, 0ull, 0ull);
     return;
   }
-  const int qx1 = min(qx0 + kQuad - 1, W - 1), qy1 = min(qy0 + kQuad - 1, H - 1);
-  const int lx = lane & 7, ly = lane >> 3;
+  // lane -> pixel: sub-block sb = lane / 16 at (4 (sb & 1), 4 (sb >> 1)) in the quadrant
+  const int sb = lane >> 4;
+  const int lx = (sb & 1) * kSub + (lane & 3), ly = (sb >> 1) * kSub + ((lane >> 2) & 3);
   const int pi = qx0 + lx, pj = qy0 + ly;
   const bool inside = pi < W && pj < H;
   const float fx = (float)lx, fy = (float)ly;
   Staged* my = stage[wid];
+  uint8_t* my_lists = &lists[wid][0][0];
+  if (lane == 0) {  // exponent -1e30: alpha 0, colour 0; evaluating it changes nothing
+    Staged z;
+    z.a = make_float4(0.f, 0.f, 0.f, 0.f);
+    z.b = make_float4(0.f, -1e30f, 0.f, 0.f);
+    z.c = make_float4(0.f, 0.f, 0.f, 0.f);
+    my[64] = z;
+  }
 
   // ranges come from this frame's sorted keys; the clamps only make a
   // corrupted table unable to send a load outside the buffers
@@ -182,12 +195,16 @@ __global__ void __launch_bounds__(256) render_kernel(
     const uint32_t k = base + lane;
     const uint32_t g = g_cur;
     const uint2 box = box_cur;
-    const bool hit = (int)(box.x & 0xffffu) <= qx1 && (int)(box.x >> 16) >= qx0 && (int)(box.y & 0xffffu) <= qy1 &&
-                     (int)(box.y >> 16) >= qy0;
-    const uint64_t mask = __ballot(hit);
-    if (hit) {
-      const uint32_t slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    const int bxl = (int)(box.x & 0xffffu), bxh = (int)(box.x >> 16);
+    const int byl = (int)(box.y & 0xffffu), byh = (int)(box.y >> 16);
+    // the box against the two sub-block columns and rows of the quadrant
+    const bool c0 = bxl <= qx0 + 3 && bxh >= qx0, c1 = bxl <= qx0 + 7 && bxh >= qx0 + 4;
+    const bool r0 = byl <= qy0 + 3 && byh >= qy0, r1 = byl <= qy0 + 7 && byh >= qy0 + 4;
+    const uint64_t m0 = __ballot(c0 && r0), m1 = __ballot(c1 && r0);
+    const uint64_t m2 = __ballot(c0 && r1), m3 = __ballot(c1 && r1);
+    const uint64_t any = m0 | m1 | m2 | m3;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if ((any >> lane) & 1ull) {
       const RenderRecord& r = rec[g];
       const double x = r.x, y = r.y;
       const float4 q = *reinterpret_cast<const float4*>(&r.qa);
@@ -196,7 +213,11 @@ __global__ void __launch_bounds__(256) render_kernel(
       st.a = make_float4((float)(x - (double)qx0), (float)(y - (double)qy0), q.x, q.y);
       st.b = make_float4(q.z, q.w, c.x, c.y);
       st.c = make_float4(c.z, __uint_as_float(g), __uint_as_float(k), 0.f);
-      my[slot] = st;
+      my[lane] = st;
+      if ((m0 >> lane) & 1ull) my_lists[0 * 64 + __popcll(m0 & lt)] = (uint8_t)lane;
+      if ((m1 >> lane) & 1ull) my_lists[1 * 64 + __popcll(m1 & lt)] = (uint8_t)lane;
+      if ((m2 >> lane) & 1ull) my_lists[2 * 64 + __popcll(m2 & lt)] = (uint8_t)lane;
+      if ((m3 >> lane) & 1ull) my_lists[3 * 64 + __popcll(m3 & lt)] = (uint8_t)lane;
     }
     // issue the next loads before evaluating this batch
     {
@@ -205,30 +226,37 @@ __global__ void __launch_bounds__(256) render_kernel(
       box_cur = k1 < e ? *reinterpret_cast<const uint2*>(&rec[g_next].box_x) : kNoBox;
       g_next = k2 < e ? min(vals[k2], n_gauss - 1) : 0u;
     }
-    if (mask == 0) continue;
+    if (any == 0) continue;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int n_hit = __popcll(mask);
-    // Pipeline: the exponent of entry i+1 is computed while entry i is
+    const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2), n3 = __popcll(m3);
+    const int n_iter = max(max(n0, n1), max(n2, n3));
+    const int my_n = sb == 0 ? n0 : sb == 1 ? n1 : sb == 2 ? n2 : n3;
+    const uint8_t* my_list = my_lists + sb * 64;
+    // Pipeline: the exponent of step i+1 is computed while step i is
     // blended (it does not depend on the transmittance).
-    float4 A = stage[wid][0].a, B = stage[wid][0].b, C = stage[wid][0].c;
+    int slot = my_n > 0 ? my_list[0] & 63 : 64;
+    float4 A = my[slot].a, B = my[slot].b, C = my[slot].c;
     float q = quad_form(A, B, fx, fy);
     float e2 = __builtin_amdgcn_exp2f(q);
-    for (int i = 0; i < n_hit; ++i) {
-      const int inext = min(i + 1, n_hit - 1);
-      const float4 An = stage[wid][inext].a, Bn = stage[wid][inext].b, Cn = stage[wid][inext].c;
+    for (int i = 0; i < n_iter; ++i) {
+      const int inext = min(i + 1, 63);
+      const int slot_n = inext < my_n ? my_list[inext] & 63 : 64;
+      const float4 An = my[slot_n].a, Bn = my[slot_n].b, Cn = my[slot_n].c;
       const float qn = quad_form(An, Bn, fx, fy);
       const float e2n = __builtin_amdgcn_exp2f(qn);
 
+      const bool live = !done & (i < my_n);
       float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
-      bool blend = !done && q >= bl.q_low;
-      float Tn = T * (1.f - a);
-      bool near_t = blend && Tn >= bl.t_band_lo && Tn <= bl.t_band_hi;
-      const bool near_low = !done && fabsf(q - bl.q_low) < bl.q_band;
+      bool blend = live & (q >= bl.q_low);
+      const bool near_low = live & (fabsf(q - bl.q_low) < bl.q_band);
+      float af = blend ? a : 0.f;
+      float Tn = fmaf(-af, T, T);  // T (1 - alpha) with one rounding
+      bool near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
       float t_exact = 0.f;
       bool stop_exact = false;
-      if (__builtin_expect(__ballot(near_low || near_t) != 0, 0)) {
+      if (__builtin_expect(__ballot(near_low | near_t) != 0, 0)) {
         // Rare (wave-uniform branch): an exponent near log2(alpha_low) is
         // decided in FP64; a transmittance near t_min is recomputed in FP64
         // by the whole wave over the list so far.
@@ -236,16 +264,17 @@ __global__ void __launch_bounds__(256) render_kernel(
           const double ad = alpha_fp64_at(rec, exact, __float_as_uint(C.y), pi, pj, bl.alpha_max_d);
           blend = ad >= bl.alpha_low_d;
           a = (float)ad;
-          Tn = T * (1.f - a);
-          near_t = blend && Tn >= bl.t_band_lo && Tn <= bl.t_band_hi;
+          af = blend ? a : 0.f;
+          Tn = fmaf(-af, T, T);
+          near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
           ++n_band;
         }
         uint64_t rm = __ballot(near_t);
-        const uint32_t k_now = __float_as_uint(C.z);
         while (rm) {
           const int L = __builtin_ctzll(rm);
           rm &= rm - 1;
           const int ri = __builtin_amdgcn_readlane(pi, L), rj = __builtin_amdgcn_readlane(pj, L);
+          const uint32_t k_now = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(C.z), L);
           const double prod = replay_fp64(rec, exact, vals, n_gauss, s, k_now, ri, rj, lane, bl);
           if (lane == L) {
             t_exact = (float)prod;
@@ -254,17 +283,17 @@ __global__ void __launch_bounds__(256) render_kernel(
           }
         }
       }
-      const float w = blend ? a * T : 0.f;
+      const float w = af * T;
       cr = fmaf(B.z, w, cr);
       cg = fmaf(B.w, w, cg);
       cb = fmaf(C.x, w, cb);
-      T = blend ? (near_t ? t_exact : Tn) : T;
+      T = near_t ? t_exact : Tn;
       nb += blend ? 1u : 0u;
       // bitwise on purpose: no short-circuit branches in the common path
       const bool t_stop = near_t ? stop_exact : (T < bl.t_min);
       const bool stop = blend & (t_stop | (nb == cap));
       stop_k = stop ? __float_as_uint(C.z) : stop_k;
-      done = done || stop;
+      done = done | stop;
       A = An;
       B = Bn;
       C = Cn;
@@ -288,11 +317,10 @@ finished:
     if (l_blend) l_blend[pix] = nb;
   }
   if (wave_sums) {
-    // per-wave partial sums for Eq. 13; reduced in a fixed order afterwards
-    // (one address per wave: no contended atomics, and reproducible)
+    // per-wave partial sums for Eq. 13, reduced by load_sums_kernel
     const unsigned long long b1 = wave_sum_u64(nb), b2 = wave_sum_u64((unsigned long long)nb * nb);
     const unsigned long long i1 = wave_sum_u64(ni), i2 = wave_sum_u64((unsigned long long)ni * ni);
-    if (lane == 0) wave_sums[4 * tile + wid] = make_ulonglong4(b1, b2, i1, i2);
+    if (lane == 0) wave_sums[4 * blockIdx.x + wid] = make_ulonglong4(b1, b2, i1, i2);
   }
   if (counters) {
     const unsigned long long nbd = wave_sum_u64(n_band), nrp = wave_sum_u64(n_replay);
@@ -303,12 +331,13 @@ finished:
   }
 }
 
-// Sums the per-wave partials into the four load sums, in a fixed order.
-__global__ void __launch_bounds__(1024) load_sums_kernel(const ulonglong4* __restrict__ wave_sums, int n,
-                                                         unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long part[16][4];
+// Adds the per-wave partials into the four load sums (zeroed by the
+// frame-init kernel). Integer sums: the result does not depend on the order.
+__global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __restrict__ wave_sums, int n,
+                                                        unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long part[4][4];
   unsigned long long a = 0, b = 0, c = 0, d = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const ulonglong4 v = wave_sums[i];
     a += v.x;
     b += v.y;
@@ -328,9 +357,9 @@ __global__ void __launch_bounds__(1024) load_sums_kernel(const ulonglong4* __res
   }
   __syncthreads();
   if (threadIdx.x < 4) {
-    unsigned long long t = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w][threadIdx.x];
-    out[threadIdx.x] = t;
+    const unsigned long long t = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
+                                 part[3][threadIdx.x];
+    if (t) atomicAdd(&out[threadIdx.x], t);
   }
 }
 
@@ -343,21 +372,24 @@ hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tile
 }
 
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
-                         const uint32_t* ranges, const uint32_t* order, void* wave_sums, int64_t n_pairs,
-                         int64_t n_gauss, const CamArgs& cam, const BlendArgs& blend, adr_frame* out,
-                         unsigned long long* counters, hipStream_t stream) {
+                         const uint32_t* ranges, const uint32_t* order, int64_t n_pairs, int64_t n_gauss,
+                         const CamArgs& cam, const BlendArgs& blend, adr_frame* out, adr_workspace* ws,
+                         hipStream_t stream) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  ulonglong4* ws4 = out->load_sums ? (ulonglong4*)wave_sums : nullptr;
+  ulonglong4* ws4 = out->load_sums ? (ulonglong4*)ws->wave_sums : nullptr;
   render_kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(
       rec, exact, vals, ranges, order, (uint32_t)n_pairs, (uint32_t)(n_gauss > 0 ? n_gauss : 1), cam, blend,
-      n_tiles, out->image, out->final_t, out->l_iter, out->l_blend, ws4, counters);
+      n_tiles, out->image, out->final_t, out->l_iter, out->l_blend, ws4, ws->dev_counters);
   return hipGetLastError();
 }
 
-hipError_t launch_load_sums(const void* wave_sums, int n_tiles, uint64_t* load_sums, hipStream_t stream) {
+hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums, hipStream_t stream) {
   if (!load_sums) return hipSuccess;
-  load_sums_kernel<<<1, 1024, 0, stream>>>((const ulonglong4*)wave_sums, 4 * n_tiles,
-                                           (unsigned long long*)load_sums);
+  const int n = 4 * n_tiles;
+  int blocks = (n + 1023) / 1024;
+  if (blocks > 64) blocks = 64;
+  load_sums_kernel<<<dim3((unsigned)blocks), 256, 0, stream>>>((const ulonglong4*)ws->wave_sums, n,
+                                                               (unsigned long long*)load_sums);
   return hipGetLastError();
 }
 

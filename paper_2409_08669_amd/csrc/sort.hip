@@ -198,21 +198,19 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
 
 int64_t sort_scratch_entries(int64_t n) {
   const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
-  // digit counts / offsets [256][nb], then the global histograms [kMaxPasses][256]
-  return (int64_t)kRadix * (nb > 0 ? nb : 1) + kMaxPasses * kRadix;
+  return (int64_t)kRadix * (nb > 0 ? nb : 1);  // digit counts / offsets [256][nb]
 }
 
+// hist: kMaxPasses x 256 words, zero on entry (the frame-init kernel clears it)
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t* scratch,
-                             int* result_buffer, hipStream_t stream) {
+                             uint32_t* hist, int* result_buffer, hipStream_t stream) {
   *result_buffer = 0;
   if (n <= 1 || n_bits <= 0) return hipSuccess;
   const int n_pass = (n_bits + 7) / 8;
   if (n_pass > kMaxPasses) return hipErrorInvalidValue;
   const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
   uint32_t* counts = scratch;
-  uint32_t* hist = counts + (int64_t)kRadix * nb;
-  hipError_t e = launch_fill_u32(hist, 0u, kMaxPasses * kRadix, stream);
-  if (e != hipSuccess) return e;
+  hipError_t e;
   int64_t hist_blocks = (n + kThreads * 16 - 1) / (kThreads * 16);
   if (hist_blocks > 2048) hist_blocks = 2048;
   digit_histogram_kernel<<<dim3((unsigned)hist_blocks), kThreads, 0, stream>>>(keys[0], n, n_pass, hist);
