@@ -54,19 +54,25 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(stage, n, n_vis, n_pairs, n_pix, n_tiles, n_coeff, n_pass):
+def algorithmic_bytes(stage, n, n_vis, n_pairs, n_pix, n_tiles, n_coeff, depth_bits):
     """Bytes the method itself must move per launch of each stage (reads +
     writes), independent of how the kernel caches them."""
     if stage == "preprocess":
-        # geometry of every Gaussian (48 B) + SH of visible ones + count out +
-        # render record (64 B) + FP64 record (32 B) + rect/depth (12 B) of visible ones
-        return n * 48 + n_vis * (12 * n_coeff) + n * 4 + n_vis * (64 + 32 + 12)
+        # geometry of every Gaussian (48 B) in, tiles_touched + depth key + id
+        # (12 B) out; SH of visible ones in, render record (64 B) + FP64
+        # record (32 B) + tile rectangle (8 B) out
+        return n * (48 + 12) + n_vis * (12 * n_coeff + 64 + 32 + 8)
     if stage == "inclusive_sum":
-        return n * 8
+        # depth order (4 B) and tiles_touched (4 B) of each visible Gaussian, offset out (4 B)
+        return n_vis * 12
     if stage == "duplicate":
-        return n_vis * 20 + n_pairs * 12
-    if stage == "sort":
-        return n_pairs * 8 + n_pass * n_pairs * 24  # histogram read + per pass read/write of key+id
+        # offsets, order and tile rectangle of each visible Gaussian, tile id + id out per pair
+        return n_vis * 16 + n_pairs * 8
+    if stage in ("depth_sort", "tile_sort"):
+        # LSD radix sort with 8-bit digits: per pass the key is read once for
+        # the digit counts, then key and id are read and written once
+        n_el, bits = (n, depth_bits) if stage == "depth_sort" else (n_pairs, math.ceil(math.log2(n_tiles)))
+        return math.ceil(bits / 8) * n_el * 20
     if stage == "ranges":
         return n_pairs * 8 + n_tiles * 8
     if stage == "render":
@@ -107,7 +113,6 @@ def main():
                load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
     stream = torch.cuda.current_stream()
     n_tiles = ((w + 15) // 16) * ((h + 15) // 16)
-    n_pass = math.ceil((32 + math.ceil(math.log2(n_tiles))) / 8)
 
     # name: (cull mode, extra flags). The last one is an ablation: the paper's
     # AABB pair culling alone, without reusing the extent inside Render.
@@ -147,7 +152,7 @@ def main():
         results[name] = dict(
             fps=args.steps / dt, ms_per_frame=1e3 * dt / args.steps, pairs=int(n_pairs),
             sum_blend=int(sums[0]), sum_iter=int(sums[2]),
-            visible=counters.get("visible"), stages_ms={k: v / args.steps for k, v in stage_sum.items()},
+            visible=counters.get("visible"), depth_bits=counters.get("depth_sort_bits"), stages_ms={k: v / args.steps for k, v in stage_sum.items()},
             band_redecisions=counters.get("band_redecisions"), t_replays=counters.get("t_replays"),
             load_mean_blend=mean_b, load_std_blend=std_b, load_mean_iter=mean_i, load_std_iter=std_i)
         images[name] = out["image"].clone()
@@ -178,7 +183,7 @@ def main():
     dom = max(kern, key=kern.get)
     per_stage = {}
     for s_, ms in kern.items():
-        b = algorithmic_bytes(s_, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, n_pass)
+        b = algorithmic_bytes(s_, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, head["depth_bits"] or 32)
         per_stage[s_] = {"ms": round(ms, 4), "algorithmic_bytes": int(b),
                          "GB/s": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                          "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}

@@ -182,7 +182,8 @@ int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
 /* Per-frame counters of the last adr_render on ws (host values; the frame
  * must have finished): [0] pairs, [1] visible Gaussians (tiles_touched > 0),
  * [2] exact-band alpha re-decisions, [3] exact-band transmittance replays,
- * [4] reserved (0). Returns the number of entries written. */
+ * [4] key bits the depth sort of the Gaussians covered (the visible depth
+ * keys' range; 8 per radix pass). Returns the number of entries written. */
 int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n);
 
 const char* adr_last_error(void);

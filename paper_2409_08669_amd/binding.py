@@ -234,7 +234,7 @@ class Workspace:
     def counters(self) -> dict:
         buf = (ctypes.c_int64 * 5)()
         k = load().adr_workspace_counters(self._h, buf, 5)
-        names = ("pairs", "visible", "band_redecisions", "t_replays", "sort_spin_limit")
+        names = ("pairs", "visible", "band_redecisions", "t_replays", "depth_sort_bits")
         return {names[i]: int(buf[i]) for i in range(k)}
 
     def close(self):

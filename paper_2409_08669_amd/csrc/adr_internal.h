@@ -114,6 +114,8 @@ struct adr_workspace {
   adr::SortBuffers depth;          // (depth key, id) of every Gaussian, sorted by depth
   uint32_t* scan_partials = nullptr;
   int64_t scan_partials_capacity = 0;
+  ulonglong4* block_parts = nullptr;  // per Preprocess workgroup: pairs, visible, depth-key min, max
+  int64_t block_parts_capacity = 0;
   // per pair
   adr::SortBuffers pairs;          // (tile id, Gaussian id), sorted by tile
   uint32_t* sort_scratch = nullptr;
@@ -139,6 +141,7 @@ struct adr_workspace {
   bool timing_valid = false;
   hipStream_t last_stream = nullptr;
   int64_t last_pairs = 0;
+  int32_t last_depth_bits = 0;  // key bits the last frame's depth sort covered
 };
 
 namespace adr {
@@ -148,6 +151,9 @@ constexpr int kCntPairs = 0;       // sum of tiles_touched (u64)
 constexpr int kCntVisible = 1;     // Gaussians with tiles_touched > 0
 constexpr int kCntBand = 2;        // FP64 re-decisions near alpha_low
 constexpr int kCntReplay = 3;      // FP64 transmittance replays near t_min
+constexpr int kCntDepthMin = 4;    // smallest depth key of a visible Gaussian
+constexpr int kCntDepthMax = 5;    // largest depth key of a visible Gaussian
+constexpr int kNotifySlots = 8;    // mapped words: pairs, visible, frame number, depth min, depth max
 constexpr int kCounterSlots = 8;
 constexpr int kHistWords = 4 * 256;  // digit histograms of up to four 8-bit passes
 
@@ -166,16 +172,18 @@ hipError_t launch_pack_scene(const adr_scene_desc& desc, const float* means, con
                              const float* quats, const float* logits, const float* sh, DeviceScene& d,
                              hipStream_t stream);
 hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_sums, hipStream_t stream);
+int64_t preprocess_blocks(int64_t n);
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
                              hipStream_t stream);
 hipError_t launch_inclusive_sum(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
                                 uint32_t* partials, hipStream_t stream);
 int64_t inclusive_sum_partials(int64_t n);
-hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint32_t* touched,
-                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
-                            uint32_t* tile_keys, uint32_t* vals, hipStream_t stream);
-hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t* scratch,
-                             uint32_t* hist, int* result_buffer, hipStream_t stream);
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint2* tile_rect, int64_t n_vis,
+                            int64_t n_pairs, int32_t tiles_x, uint32_t* tile_keys, uint32_t* vals,
+                            hipStream_t stream);
+hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
+                             uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
+                             hipStream_t stream);
 int64_t sort_scratch_entries(int64_t n);
 hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);

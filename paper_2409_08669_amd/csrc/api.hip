@@ -73,6 +73,8 @@ adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
   if ((st = ensure_sort_buffers(ws->depth, n, "depth sort")) != ADR_OK) return st;
   if ((st = grow(ws->sort_scratch, ws->sort_scratch_capacity, sort_scratch_entries(n), "sort scratch")) != ADR_OK)
     return st;
+  if ((st = grow(ws->block_parts, ws->block_parts_capacity, preprocess_blocks(n), "preprocess partials")) != ADR_OK)
+    return st;
   return grow(ws->scan_partials, ws->scan_partials_capacity, inclusive_sum_partials(n) + 1, "scan partials");
 }
 
@@ -97,7 +99,7 @@ static void free_workspace_buffers(adr_workspace* ws) {
   void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->depth.keys[0],
                   ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
                   ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->sort_scratch, ws->ranges,
-                  ws->tile_order, ws->wave_sums, ws->dev_counters, ws->hists};
+                  ws->tile_order, ws->wave_sums, ws->dev_counters, ws->hists, ws->block_parts};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ws->host_counters) (void)hipHostFree(ws->host_counters);
@@ -123,11 +125,11 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
             hipMalloc(&ws->hists, 2 * kHistWords * sizeof(uint32_t)) == hipSuccess &&
             hipHostMalloc(&ws->host_counters, kCounterSlots * sizeof(unsigned long long), hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc(&ws->notify_host, 4 * sizeof(unsigned long long),
+            hipHostMalloc(&ws->notify_host, kNotifySlots * sizeof(unsigned long long),
                           hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
   if (ok) {
     std::memset(ws->host_counters, 0, kCounterSlots * sizeof(unsigned long long));
-    std::memset(ws->notify_host, 0, 4 * sizeof(unsigned long long));
+    std::memset(ws->notify_host, 0, kNotifySlots * sizeof(unsigned long long));
     ok = hipHostGetDevicePointer((void**)&ws->notify_dev, ws->notify_host, 0) == hipSuccess;
   }
   if (!ok) {
@@ -274,7 +276,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
   // The pair count sizes everything after this point. The last Preprocess
   // workgroup writes it to mapped host memory; wait for this frame's number.
-  unsigned long long n_pairs_u = 0, n_vis_u = 0;
+  unsigned long long n_pairs_u = 0, n_vis_u = 0, dmin = 0, dmax = 0;
   if (s.n > 0) {
     volatile unsigned long long* nf = ws->notify_host;
     const auto t0 = std::chrono::steady_clock::now();
@@ -292,6 +294,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     std::atomic_thread_fence(std::memory_order_acquire);
     n_pairs_u = nf[0];
     n_vis_u = nf[1];
+    dmin = nf[3];
+    dmax = nf[4];
   }
   const int64_t n_vis = (int64_t)n_vis_u;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[2], stream));
@@ -306,23 +310,36 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if ((st = ensure_pairs(ws, n_pairs)) != ADR_OK) return st;
 
   // Stage 4a: every Gaussian by its 32-bit depth key (ties keep id order);
-  // the visible ones come first.
+  // the visible ones come first. Only the bits that vary over the visible
+  // keys are sorted: key - dmin, with every larger key (the invisible ones'
+  // all-ones key) clamped to lim, which is above every visible key.
   int dsorted = 0;  // which of the two buffers holds the result
-  ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, 32, ws->sort_scratch, ws->hists, &dsorted,
-                            stream));
+  ws->last_depth_bits = 0;
+  if (n_vis > 0) {
+    if (dmax < dmin || dmax > 0xffffffffull) {
+      set_error("adr_render: inconsistent depth-key range from Preprocess");
+      return ADR_E_HIP;
+    }
+    int dbits = bits_for((int64_t)(dmax - dmin) + 2);
+    if (dbits > 32) dbits = 32;
+    ws->last_depth_bits = dbits;
+    const uint32_t lim = dbits >= 32 ? 0xffffffffu : (uint32_t)((1ull << dbits) - 1);
+    ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, dbits, (uint32_t)dmin, lim, ws->sort_scratch,
+                              ws->hists, &dsorted, stream));
+  }
   const uint32_t* order = ws->depth.vals[dsorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
   // Stage 2: InclusiveSum of tiles_touched over the Gaussians in depth order
   ADR_HIP(launch_inclusive_sum(ws->touched, order, ws->offsets, n_vis, ws->scan_partials, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[4], stream));
   // Stage 3: DuplicateWithKeys, in depth order, keyed by tile id
-  ADR_HIP(launch_duplicate(ws->offsets, order, ws->touched, ws->tile_rect, n_vis, n_pairs, ca.tiles_x,
-                           ws->pairs.keys[0], ws->pairs.vals[0], stream));
+  ADR_HIP(launch_duplicate(ws->offsets, order, ws->tile_rect, n_vis, n_pairs, ca.tiles_x, ws->pairs.keys[0],
+                           ws->pairs.vals[0], stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[5], stream));
   // Stage 4b: stable sort by tile id; equal tiles keep the depth order
   int psorted = 0;
-  ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), ws->sort_scratch,
-                            ws->hists + kHistWords, &psorted, stream));
+  ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), 0u, 0xffffffffu,
+                            ws->sort_scratch, ws->hists + kHistWords, &psorted, stream));
   const uint32_t* tiles = ws->pairs.keys[psorted];
   const uint32_t* vals = ws->pairs.vals[psorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
@@ -395,6 +412,6 @@ extern "C" int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32
   }
   const int idx[5] = {kCntPairs, kCntVisible, kCntBand, kCntReplay, -1};
   int32_t k = 0;
-  for (; k < 5 && k < n; ++k) out[k] = idx[k] >= 0 ? (int64_t)ws->host_counters[idx[k]] : 0;
+  for (; k < 5 && k < n; ++k) out[k] = idx[k] >= 0 ? (int64_t)ws->host_counters[idx[k]] : ws->last_depth_bits;
   return k;
 }

@@ -1,43 +1,91 @@
 // DuplicateWithKeys and IdentifyTileRanges (Sec. 3.2, stages 3 and 5).
 //
-// Pair emission is pair-parallel: lane p finds its Gaussian by binary search
-// in the inclusive offsets (taken over the Gaussians in depth order), so one
-// Gaussian with a huge rectangle does not serialise a wave, and consecutive
-// lanes write consecutive pairs (coalesced). Within a Gaussian the tiles are
-// emitted row-major over its tile rectangle. Each pair carries the tile id as
-// its sort key; the depth order is already in the emission order.
+// Pair emission is pair-parallel and balanced: workgroup b writes pairs
+// [2048 b, 2048 b + 2048). Two waves find the first and the last Gaussian
+// (in depth order) whose pairs fall in that range with a 64-way search of the
+// inclusive offsets (a handful of dependent loads instead of twenty), the
+// workgroup stages those Gaussians' offsets in LDS, and each pair finds its
+// Gaussian by binary search there. One Gaussian with a huge rectangle
+// therefore spreads over many workgroups, and consecutive lanes write
+// consecutive pairs. Within a Gaussian the tiles are emitted row-major over
+// its tile rectangle. Each pair carries the tile id as its sort key; the depth
+// order is already in the emission order.
 #include "adr_internal.h"
 
 namespace adr {
 
 namespace {
 
-__global__ void __launch_bounds__(256) duplicate_kernel(const uint32_t* __restrict__ offsets,
-                                                        const uint32_t* __restrict__ order,
-                                                        const uint32_t* __restrict__ touched,
-                                                        const uint2* __restrict__ tile_rect, int64_t n_vis,
-                                                        int64_t n_pairs, int32_t tiles_x,
-                                                        uint32_t* __restrict__ tile_keys, uint32_t* __restrict__ vals) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pairs) return;
-  const uint32_t pp = (uint32_t)p;
-  // smallest r with offsets[r] > p
-  int64_t lo = 0, hi = n_vis - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (offsets[mid] > pp)
-      hi = mid;
-    else
-      lo = mid + 1;
+constexpr int kDupThreads = 256;
+constexpr int kDupPairs = 2048;  // pairs per workgroup
+
+// Smallest r in [0, n) with offsets[r] > p, for a non-decreasing array whose
+// last entry exceeds p; every lane of the wave returns it.
+__device__ uint32_t wave_search_gt(const uint32_t* __restrict__ offsets, uint32_t n, uint32_t p) {
+  const int lane = threadIdx.x & 63;
+  uint32_t lo = 0, hi = n;  // answer in [lo, hi)
+  while (hi - lo > 64) {
+    const uint32_t step = (hi - lo + 63) / 64;
+    const uint32_t at = lo + (uint32_t)lane * step;
+    const bool gt = at < hi ? offsets[at] > p : true;
+    const uint64_t m = __ballot(gt);  // the lanes from the first true one on
+    if (m == 0) {  // every sample (all below hi) is <= p: the answer lies past the last one
+      lo += 63u * step + 1u;
+      continue;
+    }
+    const int f = __ffsll((long long)m) - 1;
+    if (f == 0) return lo;
+    const uint32_t prev = lo + (uint32_t)(f - 1) * step;  // offsets[prev] <= p
+    const uint32_t cand = lo + (uint32_t)f * step;
+    lo = prev + 1;
+    hi = cand < hi ? cand + 1 : hi;
   }
-  const uint32_t g = order[lo];
-  const uint32_t k = pp - (offsets[lo] - touched[g]);
-  const uint2 r = tile_rect[g];
-  const uint32_t tx_lo = r.x & 0xffffu, tx_hi = r.x >> 16;
-  const uint32_t ty_lo = r.y & 0xffffu;
-  const uint32_t w = tx_hi - tx_lo + 1;
-  tile_keys[p] = (ty_lo + k / w) * (uint32_t)tiles_x + tx_lo + k % w;
-  vals[p] = g;
+  const uint32_t at = lo + (uint32_t)lane;
+  const bool gt = at < hi ? offsets[at] > p : true;
+  const uint64_t m = __ballot(gt);
+  return lo + (uint32_t)(__ffsll((long long)m) - 1);
+}
+
+__global__ void __launch_bounds__(kDupThreads) duplicate_kernel(const uint32_t* __restrict__ offsets,
+                                                                const uint32_t* __restrict__ order,
+                                                                const uint2* __restrict__ tile_rect, uint32_t n_vis,
+                                                                uint32_t n_pairs, int32_t tiles_x,
+                                                                uint32_t* __restrict__ tile_keys,
+                                                                uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_end[kDupPairs];  // inclusive offsets of the workgroup's Gaussians
+  __shared__ uint32_t s_range[2];
+  const int tid = threadIdx.x, wid = tid >> 6;
+  const uint32_t p0 = blockIdx.x * (uint32_t)kDupPairs;
+  const uint32_t p1 = min(p0 + (uint32_t)kDupPairs, n_pairs) - 1;  // last pair of the workgroup
+  if (wid < 2) {
+    const uint32_t r = wave_search_gt(offsets, n_vis, wid == 0 ? p0 : p1);
+    if ((tid & 63) == 0) s_range[wid] = r;
+  }
+  __syncthreads();
+  const uint32_t r_lo = s_range[0], r_hi = s_range[1];  // r_hi - r_lo < kDupPairs: each holds >= 1 pair
+  const uint32_t cnt = min(r_hi - r_lo + 1, (uint32_t)kDupPairs);
+  for (uint32_t i = tid; i < cnt; i += kDupThreads) s_end[i] = offsets[r_lo + i];
+  const uint32_t start_lo = r_lo > 0 ? offsets[r_lo - 1] : 0u;  // first pair of Gaussian r_lo
+  __syncthreads();
+  for (uint32_t p = p0 + tid; p <= p1; p += kDupThreads) {
+    uint32_t lo = 0, hi = cnt - 1;  // smallest i with s_end[i] > p
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (s_end[mid] > p)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const uint32_t first = lo > 0 ? s_end[lo - 1] : start_lo;
+    const uint32_t k = p - first;
+    const uint32_t g = order[r_lo + lo];
+    const uint2 r = tile_rect[g];
+    const uint32_t tx_lo = r.x & 0xffffu, tx_hi = r.x >> 16;
+    const uint32_t ty_lo = r.y & 0xffffu;
+    const uint32_t w = tx_hi - tx_lo + 1;
+    tile_keys[p] = (ty_lo + k / w) * (uint32_t)tiles_x + tx_lo + k % w;
+    vals[p] = g;
+  }
 }
 
 __global__ void __launch_bounds__(256) tile_ranges_kernel(const uint32_t* __restrict__ tiles, int64_t n_pairs,
@@ -85,12 +133,13 @@ __global__ void fill_u64_kernel(unsigned long long* __restrict__ p, unsigned lon
 
 }  // namespace
 
-hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint32_t* touched,
-                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
-                            uint32_t* tile_keys, uint32_t* vals, hipStream_t stream) {
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint2* tile_rect, int64_t n_vis,
+                            int64_t n_pairs, int32_t tiles_x, uint32_t* tile_keys, uint32_t* vals,
+                            hipStream_t stream) {
   if (n_pairs <= 0 || n_vis <= 0) return hipSuccess;
-  duplicate_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(
-      offsets, order, touched, tile_rect, n_vis, n_pairs, tiles_x, tile_keys, vals);
+  if (n_pairs >= (int64_t)1 << 32 || n_vis >= (int64_t)1 << 32) return hipErrorInvalidValue;
+  duplicate_kernel<<<dim3((unsigned)((n_pairs + kDupPairs - 1) / kDupPairs)), kDupThreads, 0, stream>>>(
+      offsets, order, tile_rect, (uint32_t)n_vis, (uint32_t)n_pairs, tiles_x, tile_keys, vals);
   return hipGetLastError();
 }
 

@@ -104,12 +104,42 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return v;
 }
 
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+    v = min(v, ((unsigned long long)hi << 32) | lo);
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+    v = max(v, ((unsigned long long)hi << 32) | lo);
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, (uint32_t)__shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor(v, off, 64));
+  return v;
+}
+
 __global__ void __launch_bounds__(256) preprocess_kernel(
     const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
     const float* __restrict__ planes, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, CullArgs cull,
     RenderRecord* __restrict__ rec, ExactRecord* __restrict__ exact, uint2* __restrict__ tile_rect,
     uint32_t* __restrict__ depth_key, uint32_t* __restrict__ depth_id, uint32_t* __restrict__ touched_out,
-    unsigned long long* __restrict__ counters) {
+    ulonglong4* __restrict__ block_parts) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t touched = 0;
   uint32_t dkey = 0xffffffffu;  // Gaussians without pairs sort after every visible one
@@ -246,32 +276,80 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
     depth_key[g] = dkey;
     depth_id[g] = (uint32_t)g;
   }
-  // Pair total (u64, exact) and visible count for the host.
-  __shared__ unsigned long long part[2][4];
+  // Per-workgroup pair total (u64, exact), visible count and range of the
+  // visible depth keys, reduced by the notify kernel. (Global atomics from
+  // every workgroup onto a few words serialise across the XCDs.)
+  __shared__ unsigned long long part[4][4];
+  const bool vis = touched > 0;
   const unsigned long long wt = wave_sum_u64(touched);
-  const unsigned long long wv = wave_sum_u64(touched > 0 ? 1ull : 0ull);
+  const unsigned long long wv = wave_sum_u64(vis ? 1ull : 0ull);
+  const uint32_t wmin = wave_min_u32(vis ? dkey : 0xffffffffu);
+  const uint32_t wmax = wave_max_u32(vis ? dkey : 0u);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (lane == 0) {
     part[0][wid] = wt;
     part[1][wid] = wv;
+    part[2][wid] = wmin;
+    part[3][wid] = wmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned long long st = part[0][0] + part[0][1] + part[0][2] + part[0][3];
-    const unsigned long long sv = part[1][0] + part[1][1] + part[1][2] + part[1][3];
-    if (st) atomicAdd(&counters[kCntPairs], st);
-    if (sv) atomicAdd(&counters[kCntVisible], sv);
+    ulonglong4 r;
+    r.x = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+    r.y = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    r.z = min(min(part[2][0], part[2][1]), min(part[2][2], part[2][3]));
+    r.w = max(max(part[3][0], part[3][1]), max(part[3][2], part[3][3]));
+    block_parts[blockIdx.x] = r;
   }
 }
 
 // Runs after Preprocess on the same stream (the kernel boundary makes every
-// workgroup's counts visible) and hands the pair and visible counts to the
-// host through mapped pinned memory, then publishes the frame's number.
-__global__ void notify_host_kernel(const unsigned long long* __restrict__ counters,
-                                   unsigned long long* __restrict__ notify, unsigned long long seq) {
+// workgroup's partials visible): reduces them into the frame counters and
+// hands the pair count, the visible count and the visible depth-key range to
+// the host through mapped pinned memory, then publishes the frame's number.
+__global__ void __launch_bounds__(1024) notify_host_kernel(const ulonglong4* __restrict__ block_parts, int nb,
+                                                           unsigned long long* __restrict__ counters,
+                                                           unsigned long long* __restrict__ notify,
+                                                           unsigned long long seq) {
+  __shared__ unsigned long long red[4][16];
+  unsigned long long t = 0, v = 0, mn = ~0ull, mx = 0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    const ulonglong4 r = block_parts[i];
+    t += r.x;
+    v += r.y;
+    if (r.y) {
+      mn = min(mn, r.z);
+      mx = max(mx, r.w);
+    }
+  }
+  t = wave_sum_u64(t);
+  v = wave_sum_u64(v);
+  mn = wave_min_u64(mn);
+  mx = wave_max_u64(mx);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][wid] = t;
+    red[1][wid] = v;
+    red[2][wid] = mn;
+    red[3][wid] = mx;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_store(&notify[0], counters[kCntPairs], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&notify[1], counters[kCntVisible], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    const int nw = (blockDim.x + 63) / 64;
+    for (int w = 1; w < nw; ++w) {
+      t += red[0][w];
+      v += red[1][w];
+      mn = min(mn, red[2][w]);
+      mx = max(mx, red[3][w]);
+    }
+    counters[kCntPairs] = t;
+    counters[kCntVisible] = v;
+    counters[kCntDepthMin] = mn;
+    counters[kCntDepthMax] = mx;
+    __hip_atomic_store(&notify[0], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&notify[1], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&notify[3], mn, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&notify[4], mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     __hip_atomic_store(&notify[2], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
@@ -294,15 +372,20 @@ static ShConsts make_sh_consts() {
   return s;
 }
 
+int64_t preprocess_blocks(int64_t n) { return (n + 255) / 256; }
+
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
                              hipStream_t stream) {
   if (s.n == 0) return hipSuccess;
   static const ShConsts shc = make_sh_consts();
-  dim3 grid((unsigned)((s.n + 255) / 256));
-  preprocess_kernel<<<grid, 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc, cam, cull,
-                                              ws->rec, ws->exact, ws->tile_rect, ws->depth.keys[0],
-                                              ws->depth.vals[0], ws->touched, ws->dev_counters);
-  notify_host_kernel<<<1, 64, 0, stream>>>(ws->dev_counters, ws->notify_dev, ws->frame_seq);
+  const int64_t nb = preprocess_blocks(s.n);
+  if (nb > ws->block_parts_capacity) return hipErrorInvalidValue;
+  preprocess_kernel<<<dim3((unsigned)nb), 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc,
+                                                            cam, cull, ws->rec, ws->exact, ws->tile_rect,
+                                                            ws->depth.keys[0], ws->depth.vals[0], ws->touched,
+                                                            ws->block_parts);
+  notify_host_kernel<<<1, 1024, 0, stream>>>(ws->block_parts, (int)nb, ws->dev_counters, ws->notify_dev,
+                                             ws->frame_seq);
   return hipGetLastError();
 }
 

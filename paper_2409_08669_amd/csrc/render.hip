@@ -204,6 +204,8 @@ __global__ void __launch_bounds__(256) render_kernel(
     const uint64_t m2 = __ballot(c0 && r1), m3 = __ballot(c1 && r1);
     const uint64_t any = m0 | m1 | m2 | m3;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    // every list entry past its list's length names the null slot
+    if (any != 0) reinterpret_cast<uint32_t*>(my_lists)[lane] = 0x40404040u;
     if ((any >> lane) & 1ull) {
       const RenderRecord& r = rec[g];
       const double x = r.x, y = r.y;
@@ -232,22 +234,23 @@ __global__ void __launch_bounds__(256) render_kernel(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2), n3 = __popcll(m3);
     const int n_iter = max(max(n0, n1), max(n2, n3));
-    const int my_n = sb == 0 ? n0 : sb == 1 ? n1 : sb == 2 ? n2 : n3;
     const uint8_t* my_list = my_lists + sb * 64;
-    // Pipeline: the exponent of step i+1 is computed while step i is
-    // blended (it does not depend on the transmittance).
-    int slot = my_n > 0 ? my_list[0] & 63 : 64;
+    // Pipeline: the list slot two steps ahead and the record one step ahead
+    // are read from LDS, and the exponent of step i+1 is computed, while
+    // step i is blended. Entries past a list's end are the null record,
+    // whose exponent -1e30 never blends.
+    int slot = min((int)my_list[0], 64);
     float4 A = my[slot].a, B = my[slot].b, C = my[slot].c;
+    slot = min((int)my_list[1], 64);
+    float4 An = my[slot].a, Bn = my[slot].b, Cn = my[slot].c;
     float q = quad_form(A, B, fx, fy);
     float e2 = __builtin_amdgcn_exp2f(q);
     for (int i = 0; i < n_iter; ++i) {
-      const int inext = min(i + 1, 63);
-      const int slot_n = inext < my_n ? my_list[inext] & 63 : 64;
-      const float4 An = my[slot_n].a, Bn = my[slot_n].b, Cn = my[slot_n].c;
+      const int slot_nn = min((int)my_list[min(i + 2, 63)], 64);
       const float qn = quad_form(An, Bn, fx, fy);
       const float e2n = __builtin_amdgcn_exp2f(qn);
 
-      const bool live = !done & (i < my_n);
+      const bool live = !done;
       float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
       bool blend = live & (q >= bl.q_low);
       const bool near_low = live & (fabsf(q - bl.q_low) < bl.q_band);
@@ -294,11 +297,13 @@ __global__ void __launch_bounds__(256) render_kernel(
       const bool stop = blend & (t_stop | (nb == cap));
       stop_k = stop ? __float_as_uint(C.z) : stop_k;
       done = done | stop;
-      A = An;
       B = Bn;
       C = Cn;
       q = qn;
       e2 = e2n;
+      An = my[slot_nn].a;
+      Bn = my[slot_nn].b;
+      Cn = my[slot_nn].c;
     }
     if (__ballot(!done) == 0) goto finished;
     __builtin_amdgcn_wave_barrier();  // all reads of this batch's slots before the next writes

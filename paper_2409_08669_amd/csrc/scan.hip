@@ -1,7 +1,8 @@
 // InclusiveSum (Sec. 3.2, stage 2): offsets of each Gaussian's pairs, taken
 // over the Gaussians in depth order (out[r] = sum of in[idx[r']] for r' <= r).
-// Reduce-then-scan in three launches: per-block totals, one workgroup scans
-// the totals, each block rescans its 2048 entries with its prefix.
+// Reduce-then-scan in two launches: per-block totals, then each block adds up
+// the totals of the blocks before it (a few hundred words, read from L2) and
+// rescans its 2048 entries from that prefix.
 #include "adr_internal.h"
 
 namespace adr {
@@ -49,20 +50,6 @@ __global__ void __launch_bounds__(kScanThreads) block_totals_kernel(const uint32
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-// One workgroup: exclusive scan of the block totals, in place.
-__global__ void __launch_bounds__(kScanThreads) scan_partials_kernel(uint32_t* __restrict__ partials, int64_t nb) {
-  __shared__ uint32_t smem[4];
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < nb; base += kScanThreads) {
-    const int64_t i = base + threadIdx.x;
-    const uint32_t v = i < nb ? partials[i] : 0u;
-    uint32_t total;
-    const uint32_t incl = block_incl_scan(v, smem, &total);
-    if (i < nb) partials[i] = carry + incl - v;
-    carry += total;
-  }
-}
-
 __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_t* __restrict__ in,
                                                                    const uint32_t* __restrict__ idx, int64_t n,
                                                                    const uint32_t* __restrict__ partials,
@@ -76,9 +63,13 @@ __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_
     v[i] = base + i < n ? in[idx[base + i]] : 0u;
     s += v[i];
   }
-  uint32_t total;
+  // prefix of the earlier blocks' totals
+  uint32_t before = 0;
+  for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanThreads) before += partials[b];
+  uint32_t total, prefix;
+  (void)block_incl_scan(before, smem, &prefix);
   const uint32_t incl = block_incl_scan(s, smem, &total);
-  uint32_t run = partials[blockIdx.x] + incl - s;
+  uint32_t run = prefix + incl - s;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     run += v[i];
@@ -95,7 +86,6 @@ hipError_t launch_inclusive_sum(const uint32_t* in, const uint32_t* idx, uint32_
   if (n <= 0) return hipSuccess;
   const int64_t nb = inclusive_sum_partials(n);
   block_totals_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, idx, n, partials);
-  scan_partials_kernel<<<1, kScanThreads, 0, stream>>>(partials, nb);
   scan_blocks_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, idx, n, partials, out);
   return hipGetLastError();
 }

@@ -7,6 +7,12 @@
 // at 1080p) groups them by tile without disturbing the depth order. Each pair
 // is moved in two passes instead of the five or six its 38-47 key bits need.
 //
+// A pass only looks at the bits that vary: keys are mapped to
+// min(key - bias, lim) before the digit is taken, which keeps their order
+// (every key above lim is an invisible Gaussian's all-ones key, and those
+// tie). With the bias at the smallest visible depth key the 32-bit depth keys
+// of a scene usually need three 8-bit passes instead of four.
+//
 // Each pass is reduce-then-scan: per-workgroup digit counts, one workgroup
 // per digit scans them into scatter offsets, and a downsweep ranks 4096 keys
 // per workgroup in LDS and scatters them. Ranking is stable and uses wave64
@@ -46,27 +52,19 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* smem4)
   return s + before - v;
 }
 
-// Digit counts of every pass in one read of the keys.
-__global__ void __launch_bounds__(kThreads) digit_histogram_kernel(const uint32_t* __restrict__ keys, int64_t n,
-                                                                   int n_pass, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[kMaxPasses][kRadix];
-  for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kThreads) (&h[0][0])[i] = 0u;
-  __syncthreads();
-  const int64_t stride = (int64_t)gridDim.x * kThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
-    const uint32_t k = keys[i];
-    for (int p = 0; p < n_pass; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 0xffu], 1u);
-  }
-  __syncthreads();
-  for (int p = 0; p < n_pass; ++p) {
-    const uint32_t c = h[p][threadIdx.x];
-    if (c) atomicAdd(&hist[p * kRadix + threadIdx.x], c);
-  }
+struct KeyMap {
+  uint32_t bias;
+  uint32_t lim;
+};
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t k, KeyMap km, int shift) {
+  const uint32_t m = min(k - km.bias, km.lim);
+  return (m >> shift) & 0xffu;
 }
 
 // Per-workgroup digit counts of one pass: counts[d * nb + b].
 __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __restrict__ kin, int64_t n, int shift,
-                                                           uint32_t* __restrict__ counts, int64_t nb) {
+                                                           KeyMap km, uint32_t* __restrict__ counts, int64_t nb) {
   __shared__ uint32_t wh[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int i = tid; i < 4 * kRadix; i += kThreads) (&wh[0][0])[i] = 0u;
@@ -75,24 +73,22 @@ __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __res
 #pragma unroll 4
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
-    if (idx < n) atomicAdd(&wh[wid][(kin[idx] >> shift) & 0xffu], 1u);
+    if (idx < n) atomicAdd(&wh[wid][digit_of(kin[idx], km, shift)], 1u);
   }
   __syncthreads();
   counts[(int64_t)tid * nb + blockIdx.x] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
 }
 
-// One workgroup per digit d: offsets[d * nb + b] = (keys with a smaller digit)
-// + (keys with digit d in earlier workgroups).
+// One workgroup per digit d: counts[d * nb + b] becomes the number of keys
+// with digit d in workgroups before b, and totals[d] the digit's total. (The
+// downsweep adds the totals of the smaller digits itself, so no workgroup
+// waits for another and no global atomics are needed.)
 __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __restrict__ counts, int64_t nb,
-                                                                 const uint32_t* __restrict__ hist) {
+                                                                 uint32_t* __restrict__ totals) {
   __shared__ uint32_t scan_tmp[4];
-  __shared__ uint32_t s_base;
   __shared__ uint32_t s_last;
   const int d = blockIdx.x;
-  const uint32_t base = block_excl_scan(hist[threadIdx.x], scan_tmp);
-  if ((int)threadIdx.x == d) s_base = base;
-  __syncthreads();
-  uint32_t carry = s_base;
+  uint32_t carry = 0;
   uint32_t* row = counts + (int64_t)d * nb;
   for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
     const int64_t b = b0 + threadIdx.x;
@@ -104,6 +100,7 @@ __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __res
     carry += s_last;
     __syncthreads();
   }
+  if (threadIdx.x == 0) totals[d] = carry;
 }
 
 // Stable rank of the workgroup's 4096 keys and scatter to the offsets of the
@@ -111,8 +108,9 @@ __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __res
 __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                             int64_t n, int shift, const uint32_t* __restrict__ offsets,
-                                                             int64_t nb) {
+                                                             int64_t n, int shift, KeyMap km,
+                                                             const uint32_t* __restrict__ offsets, int64_t nb,
+                                                             const uint32_t* __restrict__ totals) {
   __shared__ uint32_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
   __shared__ uint32_t wcnt[4][kRadix];
@@ -123,7 +121,9 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const uint32_t bid = blockIdx.x;
   for (int i = tid; i < 4 * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0u;
-  glob_base[tid] = offsets[(int64_t)tid * nb + bid];
+  // start of digit tid's run in the output: keys with a smaller digit, plus
+  // keys with this digit in earlier workgroups
+  glob_base[tid] = block_excl_scan(totals[tid], scan_tmp) + offsets[(int64_t)tid * nb + bid];
   __syncthreads();
   const int64_t wave_base = (int64_t)bid * kTileKeys + (int64_t)wid * (kItems * 64);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
     const bool valid = idx < n;
-    const uint32_t d = (k[r] >> shift) & 0xffu;
+    const uint32_t d = digit_of(k[r], km, shift);
     // lanes of this row holding the same digit, from one ballot per digit bit
     uint64_t m = __ballot(valid);
 #pragma unroll
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   for (int r = 0; r < kItems; ++r) {
     const int64_t idx = wave_base + r * 64 + lane;
     if (idx < n) {
-      const uint32_t dd = (k[r] >> shift) & 0xffu;
+      const uint32_t dd = digit_of(k[r], km, shift);
       const uint32_t pos = blk_start[dd] + wcnt[wid][dd] + rank[r];
       skeys[pos] = k[r];
       svals[pos] = v[r];
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   const int count = left < kTileKeys ? (int)left : kTileKeys;
   for (int i = tid; i < count; i += kThreads) {
     const uint32_t key = skeys[i];
-    const uint32_t dd = (key >> shift) & 0xffu;
+    const uint32_t dd = digit_of(key, km, shift);
     const uint32_t o = glob_base[dd] + (uint32_t)i - blk_start[dd];
     if (o < (uint64_t)n) {  // always true for a correct ranking; keeps a fault impossible
       kout[o] = key;
@@ -201,26 +201,25 @@ int64_t sort_scratch_entries(int64_t n) {
   return (int64_t)kRadix * (nb > 0 ? nb : 1);  // digit counts / offsets [256][nb]
 }
 
-// hist: kMaxPasses x 256 words, zero on entry (the frame-init kernel clears it)
-hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t* scratch,
-                             uint32_t* hist, int* result_buffer, hipStream_t stream) {
+// Stable sort of (key, value) by min(key - bias, lim), whose n_bits low bits
+// are all that vary. totals: 256 words of scratch.
+hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
+                             uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
+                             hipStream_t stream) {
   *result_buffer = 0;
   if (n <= 1 || n_bits <= 0) return hipSuccess;
   const int n_pass = (n_bits + 7) / 8;
   if (n_pass > kMaxPasses) return hipErrorInvalidValue;
   const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
   uint32_t* counts = scratch;
+  const KeyMap km{bias, lim};
   hipError_t e;
-  int64_t hist_blocks = (n + kThreads * 16 - 1) / (kThreads * 16);
-  if (hist_blocks > 2048) hist_blocks = 2048;
-  digit_histogram_kernel<<<dim3((unsigned)hist_blocks), kThreads, 0, stream>>>(keys[0], n, n_pass, hist);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   int cur = 0;
   for (int p = 0; p < n_pass; ++p) {
-    upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, counts, nb);
-    digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, hist + p * kRadix);
+    upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
+    digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
     downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
-                                                                    vals[cur ^ 1], n, 8 * p, counts, nb);
+                                                                    vals[cur ^ 1], n, 8 * p, km, counts, nb, totals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
