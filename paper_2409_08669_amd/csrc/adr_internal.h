@@ -81,6 +81,7 @@ struct BlendArgs {
   float t_min;
   float q_low;              // log2(alpha_low) rounded to float
   float q_band;             // half-width of the FP64 re-decision band on q
+  float q_cand;             // q_low - 2 q_band: entries below it cannot blend or enter the band
   float t_band_lo, t_band_hi; // fp32 transmittances that trigger an FP64 replay
   double alpha_low_d, alpha_max_d, t_min_d;
   float bg[3];

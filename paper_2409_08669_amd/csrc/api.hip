@@ -258,6 +258,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     bl.t_band_lo = 1.f;
     bl.t_band_hi = 0.f;
   }
+  bl.q_cand = bl.q_low - 2.0f * bl.q_band;
 
   if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
   if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;

@@ -30,7 +30,6 @@ namespace {
 struct alignas(16) Staged {
   float4 a;  // x - qx0, y - qy0, qa, qb
   float4 b;  // qc, ql, r, g
-  float4 c;  // b, gid bits, list index bits, 0
 };
 
 constexpr int kSub = 4;  // 4 x 4 pixel sub-blocks, 16 lanes each
@@ -101,6 +100,69 @@ __device__ __noinline__ double replay_fp64(const RenderRecord* __restrict__ rec,
   return wave_prod_f64(prod);
 }
 
+// Marks v as needed here: its load stays where it was issued, one loop
+// iteration ahead of its use, instead of being moved down next to the use
+// (where its latency would stall the step).
+__device__ __forceinline__ void ready(const float4& v) {
+  asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
+__device__ __forceinline__ void ready(float v) { asm volatile("" ::"v"(v)); }
+
+// Index of the lowest set bit of m, which is cleared; 64 (the null slot)
+// once m is empty.
+__device__ __forceinline__ int next_slot(uint64_t& m) {
+  const int slot = m ? (int)__builtin_ctzll(m) : 64;
+  m &= m - 1;
+  return slot;
+}
+
+// Cull box of Gaussian g (first 8 bytes of its record).
+__device__ __forceinline__ uint2 load_box(const RenderRecord* __restrict__ rec, uint32_t g) {
+  return *reinterpret_cast<const uint2*>(&rec[g].box_x);
+}
+
+// Ballots of one batch: bit l of m[t] is set when the box of lane l's entry
+// meets sub-block t of the quadrant at (qx0, qy0).
+struct SubMasks {
+  uint64_t m[4];
+  __device__ bool any_lane(int lane) const { return (((m[0] | m[1] | m[2] | m[3]) >> lane) & 1ull) != 0; }
+};
+
+__device__ __forceinline__ SubMasks sub_masks(uint2 box, int qx0, int qy0) {
+  const int bxl = (int)(box.x & 0xffffu), bxh = (int)(box.x >> 16);
+  const int byl = (int)(box.y & 0xffffu), byh = (int)(box.y >> 16);
+  const bool c0 = bxl <= qx0 + 3 && bxh >= qx0, c1 = bxl <= qx0 + 7 && bxh >= qx0 + 4;
+  const bool r0 = byl <= qy0 + 3 && byh >= qy0, r1 = byl <= qy0 + 7 && byh >= qy0 + 4;
+  SubMasks s;
+  s.m[0] = __ballot(c0 && r0);
+  s.m[1] = __ballot(c1 && r0);
+  s.m[2] = __ballot(c0 && r1);
+  s.m[3] = __ballot(c1 && r1);
+  return s;
+}
+
+// The part of a render record the blend stages (centre, exponent
+// coefficients, colour), loaded one batch ahead of its use.
+struct Fetched {
+  double x, y;
+  float4 q;
+  float r, g, b;
+};
+
+__device__ __forceinline__ Fetched fetch(const RenderRecord* __restrict__ rec, uint32_t g) {
+  const RenderRecord& r = rec[g];
+  Fetched f;
+  f.x = r.x;
+  f.y = r.y;
+  f.q = *reinterpret_cast<const float4*>(&r.qa);
+  const float4 c = *reinterpret_cast<const float4*>(&r.r);
+  f.r = c.x;
+  f.g = c.y;
+  f.b = c.z;
+  return f;
+}
+
 // Longest lists first: workgroups start in launch order, so the tiles whose
 // waves run longest (the heavy-load pixels of Sec. 4.4) start first and the
 // short ones fill in around them. Buckets of floor(log2(length)), longest
@@ -137,14 +199,87 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __rest
   }
 }
 
+// Per-pixel blend state (Eqs. 2-3) and its load counters.
+struct Pixel {
+  float T, cr, cg, cb;
+  uint32_t nb;      // blended entries (l_blend)
+  uint32_t stop_k;  // list position of the entry that stopped the pixel
+  uint32_t n_rare;   // FP64 re-decisions (low 16 bits) and replays (high 16 bits)
+  bool done;
+};
+
+// One front-to-back blend of a staged Gaussian (A, B, C) at the lane's
+// pixel: alpha from the FP32 exponent, re-decided in FP64 near
+// log2(alpha_low); the transmittance recomputed in FP64 by the whole wave
+// when it lands near t_min. Every lane of the wave must call it.
+__device__ __forceinline__ void blend_step(Pixel& px, const float4& A, const float4& B, float blue, int slot,
+                                           uint32_t base, const uint32_t* gids, float fx, float fy, int pi, int pj,
+                                           int lane, uint32_t cap, uint32_t s,
+                                           const RenderRecord* __restrict__ rec,
+                                           const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
+                                           uint32_t n_gauss, const BlendArgs& bl) {
+  const float q = quad_form(A, B, fx, fy);
+  const float e2 = __builtin_amdgcn_exp2f(q);
+  const bool live = !px.done;
+  float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
+  bool blend = live & (q >= bl.q_low);
+  const bool near_low = live & (fabsf(q - bl.q_low) < bl.q_band);
+  float af = blend ? a : 0.f;
+  float Tn = fmaf(-af, px.T, px.T);  // T (1 - alpha) with one rounding
+  bool near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
+  float t_exact = 0.f;
+  bool stop_exact = false;
+  if (__builtin_expect(__ballot(near_low | near_t) != 0, 0)) {
+    // Rare (wave-uniform branch): an exponent near log2(alpha_low) is
+    // decided in FP64; a transmittance near t_min is recomputed in FP64 by
+    // the whole wave over the list so far.
+    if (near_low) {
+      const double ad = alpha_fp64_at(rec, exact, gids[slot], pi, pj, bl.alpha_max_d);
+      blend = ad >= bl.alpha_low_d;
+      a = (float)ad;
+      af = blend ? a : 0.f;
+      Tn = fmaf(-af, px.T, px.T);
+      near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
+      px.n_rare += 1u;
+    }
+    uint64_t rm = __ballot(near_t);
+    while (rm) {
+      const int L = __builtin_ctzll(rm);
+      rm &= rm - 1;
+      const int ri = __builtin_amdgcn_readlane(pi, L), rj = __builtin_amdgcn_readlane(pj, L);
+      const uint32_t k_now = base + (uint32_t)__builtin_amdgcn_readlane(slot, L);
+      const double prod = replay_fp64(rec, exact, vals, n_gauss, s, k_now, ri, rj, lane, bl);
+      if (lane == L) {
+        t_exact = (float)prod;
+        stop_exact = prod < bl.t_min_d;
+        px.n_rare += 1u << 16;
+      }
+    }
+  }
+  const float w = af * px.T;
+  px.cr = fmaf(B.z, w, px.cr);
+  px.cg = fmaf(B.w, w, px.cg);
+  px.cb = fmaf(blue, w, px.cb);
+  px.T = near_t ? t_exact : Tn;
+  px.nb += blend ? 1u : 0u;
+  // bitwise on purpose: no short-circuit branches in the common path
+  const bool t_stop = near_t ? stop_exact : (px.T < bl.t_min);
+  const bool stop = blend & (t_stop | (px.nb == cap));
+  px.stop_k = stop ? base + (uint32_t)slot : px.stop_k;
+  px.done = px.done | stop;
+}
+
 __global__ void __launch_bounds__(256) render_kernel(
     const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, uint32_t n_pairs, uint32_t n_gauss,
     CamArgs cam, BlendArgs bl, int n_tiles, float* __restrict__ image, float* __restrict__ final_t,
     uint32_t* __restrict__ l_iter, uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums,
     unsigned long long* __restrict__ counters) {
-  __shared__ Staged stage[4][65];      // slot 64: a null record for lanes past their list's end
-  __shared__ uint8_t lists[4][4][64];  // per wave, per sub-block: staged slots in list order
+  // per wave, per batch slot (= list position - batch start): the staged
+  // record, its blue and its Gaussian id; slot 64 is a null record
+  __shared__ Staged stage[4][65];
+  __shared__ float stage_blue[4][65];
+  __shared__ uint32_t stage_gid[4][65];
   const int tile = (int)min(order[blockIdx.x], (uint32_t)(n_tiles - 1));
   const int W = cam.width, H = cam.height;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -162,173 +297,184 @@ __global__ void __launch_bounds__(256) render_kernel(
   const bool inside = pi < W && pj < H;
   const float fx = (float)lx, fy = (float)ly;
   Staged* my = stage[wid];
-  uint8_t* my_lists = &lists[wid][0][0];
+  float* my_blue = stage_blue[wid];
+  uint32_t* my_gid = stage_gid[wid];
   if (lane == 0) {  // exponent -1e30: alpha 0, colour 0; evaluating it changes nothing
     Staged z;
     z.a = make_float4(0.f, 0.f, 0.f, 0.f);
     z.b = make_float4(0.f, -1e30f, 0.f, 0.f);
-    z.c = make_float4(0.f, 0.f, 0.f, 0.f);
     my[64] = z;
+    my_blue[64] = 0.f;
+    my_gid[64] = 0u;
   }
 
   // ranges come from this frame's sorted keys; the clamps only make a
   // corrupted table unable to send a load outside the buffers
   const uint32_t e = min(ranges[2 * tile + 1], n_pairs);
   const uint32_t s = min(ranges[2 * tile], e);
-  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
-  uint32_t nb = 0;
-  uint32_t stop_k = 0xffffffffu;
-  bool done = !inside;
-  uint32_t n_band = 0, n_replay = 0;
+  Pixel px;
+  px.T = 1.f;
+  px.cr = px.cg = px.cb = 0.f;
+  px.nb = 0;
+  px.stop_k = 0xffffffffu;
+  px.n_rare = 0;
+  px.done = !inside;
   const uint32_t cap = bl.lb_cap > 0 ? (uint32_t)bl.lb_cap : 0xffffffffu;
   // The longest lists bound the kernel's duration: let their waves issue
   // first on a shared SIMD (wave priority only; no effect on results).
   if (e - s >= kLongList) __builtin_amdgcn_s_setprio(3);
 
-  // Two-deep software pipeline over batches: while batch b is evaluated the
-  // boxes of batch b+1 and the ids of batch b+2 are in flight.
+  // Batches of 64 list entries, software-pipelined: while batch b is
+  // evaluated, the records of batch b+1's hits, the cull boxes of batch b+2
+  // and the ids of batch b+3 are in flight.
+  // Every prefetch load is unconditional, so that nothing waits for it
+  // before its use one iteration later: list positions past the end read the
+  // last entry (their boxes are replaced by an empty one at use), and lanes
+  // whose entry misses the quadrant read record 0 (one shared cache line).
   const uint2 kNoBox = make_uint2(1u, 1u);  // lo 1 > hi 0: empty
-  uint32_t g_cur = s + lane < e ? min(vals[s + lane], n_gauss - 1) : 0u;
-  uint2 box_cur = s + lane < e ? *reinterpret_cast<const uint2*>(&rec[g_cur].box_x) : kNoBox;
-  uint32_t g_next = s + 64 + lane < e ? min(vals[s + 64 + lane], n_gauss - 1) : 0u;
+  const uint32_t last = e > s ? e - 1 : s;  // the loop below runs only when e > s
+  uint32_t g_b = 0, g_n1 = 0, raw_n2 = 0;
+  uint2 box_n1 = kNoBox;
+  SubMasks hm = sub_masks(kNoBox, qx0, qy0);
+  Fetched f_b{};
+  if (e > s) {
+    g_b = min(vals[min(s + lane, last)], n_gauss - 1);
+    g_n1 = min(vals[min(s + 64 + lane, last)], n_gauss - 1);
+    raw_n2 = vals[min(s + 128 + lane, last)];
+    box_n1 = load_box(rec, g_n1);
+    hm = sub_masks(s + lane < e ? load_box(rec, g_b) : kNoBox, qx0, qy0);
+    f_b = fetch(rec, hm.any_lane(lane) ? g_b : 0u);
+  }
   for (uint32_t base = s; base < e; base += 64) {
-    const uint32_t k = base + lane;
-    const uint32_t g = g_cur;
-    const uint2 box = box_cur;
-    const int bxl = (int)(box.x & 0xffffu), bxh = (int)(box.x >> 16);
-    const int byl = (int)(box.y & 0xffffu), byh = (int)(box.y >> 16);
-    // the box against the two sub-block columns and rows of the quadrant
-    const bool c0 = bxl <= qx0 + 3 && bxh >= qx0, c1 = bxl <= qx0 + 7 && bxh >= qx0 + 4;
-    const bool r0 = byl <= qy0 + 3 && byh >= qy0, r1 = byl <= qy0 + 7 && byh >= qy0 + 4;
-    const uint64_t m0 = __ballot(c0 && r0), m1 = __ballot(c1 && r0);
-    const uint64_t m2 = __ballot(c0 && r1), m3 = __ballot(c1 && r1);
-    const uint64_t any = m0 | m1 | m2 | m3;
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // every list entry past its list's length names the null slot
-    if (any != 0) reinterpret_cast<uint32_t*>(my_lists)[lane] = 0x40404040u;
+    const uint64_t any = hm.m[0] | hm.m[1] | hm.m[2] | hm.m[3];
     if ((any >> lane) & 1ull) {
-      const RenderRecord& r = rec[g];
-      const double x = r.x, y = r.y;
-      const float4 q = *reinterpret_cast<const float4*>(&r.qa);
-      const float4 c = *reinterpret_cast<const float4*>(&r.r);
       Staged st;
-      st.a = make_float4((float)(x - (double)qx0), (float)(y - (double)qy0), q.x, q.y);
-      st.b = make_float4(q.z, q.w, c.x, c.y);
-      st.c = make_float4(c.z, __uint_as_float(g), __uint_as_float(k), 0.f);
+      st.a = make_float4((float)(f_b.x - (double)qx0), (float)(f_b.y - (double)qy0), f_b.q.x, f_b.q.y);
+      st.b = make_float4(f_b.q.z, f_b.q.w, f_b.r, f_b.g);
       my[lane] = st;
-      if ((m0 >> lane) & 1ull) my_lists[0 * 64 + __popcll(m0 & lt)] = (uint8_t)lane;
-      if ((m1 >> lane) & 1ull) my_lists[1 * 64 + __popcll(m1 & lt)] = (uint8_t)lane;
-      if ((m2 >> lane) & 1ull) my_lists[2 * 64 + __popcll(m2 & lt)] = (uint8_t)lane;
-      if ((m3 >> lane) & 1ull) my_lists[3 * 64 + __popcll(m3 & lt)] = (uint8_t)lane;
+      my_blue[lane] = f_b.b;
+      my_gid[lane] = g_b;
     }
-    // issue the next loads before evaluating this batch
-    {
-      const uint32_t k1 = base + 64 + lane, k2 = base + 128 + lane;
-      g_cur = g_next;
-      box_cur = k1 < e ? *reinterpret_cast<const uint2*>(&rec[g_next].box_x) : kNoBox;
-      g_next = k2 < e ? min(vals[k2], n_gauss - 1) : 0u;
-    }
+    // the sub-block's entries of this batch, in list order: the set bits
+    uint64_t my_mask = sb == 0 ? hm.m[0] : sb == 1 ? hm.m[1] : sb == 2 ? hm.m[2] : hm.m[3];
+    const int n_iter = max(max(__popcll(hm.m[0]), __popcll(hm.m[1])), max(__popcll(hm.m[2]), __popcll(hm.m[3])));
+    // issue the next batches' loads before evaluating this one
+    hm = sub_masks(base + 64 + lane < e ? box_n1 : kNoBox, qx0, qy0);
+    g_b = g_n1;
+    f_b = fetch(rec, hm.any_lane(lane) ? g_b : 0u);
+    g_n1 = min(raw_n2, n_gauss - 1);
+    box_n1 = load_box(rec, g_n1);
+    raw_n2 = vals[min(base + 192 + lane, last)];
     if (any == 0) continue;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2), n3 = __popcll(m3);
-    const int n_iter = max(max(n0, n1), max(n2, n3));
-    const uint8_t* my_list = my_lists + sb * 64;
-    // Pipeline: the list slot two steps ahead and the record one step ahead
-    // are read from LDS, and the exponent of step i+1 is computed, while
-    // step i is blended. Entries past a list's end are the null record,
-    // whose exponent -1e30 never blends.
-    int slot = min((int)my_list[0], 64);
-    float4 A = my[slot].a, B = my[slot].b, C = my[slot].c;
-    slot = min((int)my_list[1], 64);
-    float4 An = my[slot].a, Bn = my[slot].b, Cn = my[slot].c;
-    float q = quad_form(A, B, fx, fy);
-    float e2 = __builtin_amdgcn_exp2f(q);
-    for (int i = 0; i < n_iter; ++i) {
-      const int slot_nn = min((int)my_list[min(i + 2, 63)], 64);
-      const float qn = quad_form(An, Bn, fx, fy);
-      const float e2n = __builtin_amdgcn_exp2f(qn);
 
-      const bool live = !done;
-      float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
-      bool blend = live & (q >= bl.q_low);
-      const bool near_low = live & (fabsf(q - bl.q_low) < bl.q_band);
-      float af = blend ? a : 0.f;
-      float Tn = fmaf(-af, T, T);  // T (1 - alpha) with one rounding
-      bool near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
-      float t_exact = 0.f;
-      bool stop_exact = false;
-      if (__builtin_expect(__ballot(near_low | near_t) != 0, 0)) {
-        // Rare (wave-uniform branch): an exponent near log2(alpha_low) is
-        // decided in FP64; a transmittance near t_min is recomputed in FP64
-        // by the whole wave over the list so far.
-        if (near_low) {
-          const double ad = alpha_fp64_at(rec, exact, __float_as_uint(C.y), pi, pj, bl.alpha_max_d);
-          blend = ad >= bl.alpha_low_d;
-          a = (float)ad;
-          af = blend ? a : 0.f;
-          Tn = fmaf(-af, T, T);
-          near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
-          ++n_band;
-        }
-        uint64_t rm = __ballot(near_t);
-        while (rm) {
-          const int L = __builtin_ctzll(rm);
-          rm &= rm - 1;
-          const int ri = __builtin_amdgcn_readlane(pi, L), rj = __builtin_amdgcn_readlane(pj, L);
-          const uint32_t k_now = (uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(C.z), L);
-          const double prod = replay_fp64(rec, exact, vals, n_gauss, s, k_now, ri, rj, lane, bl);
-          if (lane == L) {
-            t_exact = (float)prod;
-            stop_exact = prod < bl.t_min_d;
-            ++n_replay;
-          }
-        }
+    // Phase 1, candidates: the 16 lanes of a sub-block step through its
+    // entries (lowest set bit first) and mark, per pixel, the batch slots
+    // whose exponent reaches log2(alpha_low) less a margin twice the FP64
+    // band. No step depends on the previous one; two register sets alternate
+    // so that each record is read from LDS one step before its use. Every
+    // unmarked entry has alpha < alpha_low at this pixel in FP32 and lies
+    // outside the band: its blend would leave T and the colour bitwise
+    // unchanged. (Steps past a list's end read the null slot.)
+    uint64_t cand = 0;
+    {
+      int s0 = next_slot(my_mask), s1 = next_slot(my_mask);
+      float4 A0 = my[s0].a, B0 = my[s0].b, A1, B1;
+      ready(A0);
+      ready(B0);
+#pragma unroll 1
+      for (int i = 0; i < n_iter; i += 2) {
+        A1 = my[s1].a;
+        B1 = my[s1].b;
+        __builtin_amdgcn_sched_barrier(0);  // issue the reads here, one step before their use
+        float q = quad_form(A0, B0, fx, fy);
+        cand |= (q >= bl.q_cand && s0 < 64) ? (1ull << (s0 & 63)) : 0ull;
+        s0 = next_slot(my_mask);
+        __builtin_amdgcn_sched_barrier(0);  // the step above completes before the wait below
+        ready(A1);
+        ready(B1);
+        A0 = my[s0].a;
+        B0 = my[s0].b;
+        __builtin_amdgcn_sched_barrier(0);
+        q = quad_form(A1, B1, fx, fy);
+        cand |= (q >= bl.q_cand && s1 < 64) ? (1ull << (s1 & 63)) : 0ull;
+        s1 = next_slot(my_mask);
+        __builtin_amdgcn_sched_barrier(0);
+        ready(A0);
+        ready(B0);
       }
-      const float w = af * T;
-      cr = fmaf(B.z, w, cr);
-      cg = fmaf(B.w, w, cg);
-      cb = fmaf(C.x, w, cb);
-      T = near_t ? t_exact : Tn;
-      nb += blend ? 1u : 0u;
-      // bitwise on purpose: no short-circuit branches in the common path
-      const bool t_stop = near_t ? stop_exact : (T < bl.t_min);
-      const bool stop = blend & (t_stop | (nb == cap));
-      stop_k = stop ? __float_as_uint(C.z) : stop_k;
-      done = done | stop;
-      B = Bn;
-      C = Cn;
-      q = qn;
-      e2 = e2n;
-      An = my[slot_nn].a;
-      Bn = my[slot_nn].b;
-      Cn = my[slot_nn].c;
     }
-    if (__ballot(!done) == 0) goto finished;
+    // Phase 2, blending: each lane walks its candidates in slot order, which
+    // is list (depth) order, with the exact decision logic; two register
+    // sets alternate as above. The wave steps while any lane has candidates
+    // left; a lane that stops drops its remaining ones.
+    {
+      uint64_t cm = px.done ? 0ull : cand;
+      int s0 = next_slot(cm), s1 = next_slot(cm);
+      float4 A0 = my[s0].a, B0 = my[s0].b, A1, B1;
+      float b0 = my_blue[s0], b1;
+      ready(A0);
+      ready(B0);
+      ready(b0);
+#pragma unroll 1
+      while (__ballot(s0 != 64) != 0) {
+        A1 = my[s1].a;
+        B1 = my[s1].b;
+        b1 = my_blue[s1];
+        __builtin_amdgcn_sched_barrier(0);
+        blend_step(px, A0, B0, b0, s0, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
+        if (px.done) {
+          cm = 0;
+          s1 = 64;
+        }
+        s0 = next_slot(cm);
+        __builtin_amdgcn_sched_barrier(0);
+        ready(A1);
+        ready(B1);
+        ready(b1);
+        if (__ballot(s1 != 64) == 0) break;
+        A0 = my[s0].a;
+        B0 = my[s0].b;
+        b0 = my_blue[s0];
+        __builtin_amdgcn_sched_barrier(0);
+        blend_step(px, A1, B1, b1, s1, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
+        if (px.done) {
+          cm = 0;
+          s0 = 64;
+        }
+        s1 = next_slot(cm);
+        __builtin_amdgcn_sched_barrier(0);
+        ready(A0);
+        ready(B0);
+        ready(b0);
+      }
+    }
+    if (__ballot(!px.done) == 0) goto finished;
     __builtin_amdgcn_wave_barrier();  // all reads of this batch's slots before the next writes
   }
 finished:
   uint32_t ni = 0;
   if (inside) {
-    ni = stop_k != 0xffffffffu ? stop_k - s + 1 : e - s;
+    ni = px.stop_k != 0xffffffffu ? px.stop_k - s + 1 : e - s;
     const int64_t pix = (int64_t)pj * W + pi;
     const int64_t plane = (int64_t)W * H;
-    image[pix] = cr + T * bl.bg[0];
-    image[plane + pix] = cg + T * bl.bg[1];
-    image[2 * plane + pix] = cb + T * bl.bg[2];
-    if (final_t) final_t[pix] = T;
+    image[pix] = px.cr + px.T * bl.bg[0];
+    image[plane + pix] = px.cg + px.T * bl.bg[1];
+    image[2 * plane + pix] = px.cb + px.T * bl.bg[2];
+    if (final_t) final_t[pix] = px.T;
     if (l_iter) l_iter[pix] = ni;
-    if (l_blend) l_blend[pix] = nb;
+    if (l_blend) l_blend[pix] = px.nb;
   }
   if (wave_sums) {
     // per-wave partial sums for Eq. 13, reduced by load_sums_kernel
-    const unsigned long long b1 = wave_sum_u64(nb), b2 = wave_sum_u64((unsigned long long)nb * nb);
+    const unsigned long long b1 = wave_sum_u64(px.nb), b2 = wave_sum_u64((unsigned long long)px.nb * px.nb);
     const unsigned long long i1 = wave_sum_u64(ni), i2 = wave_sum_u64((unsigned long long)ni * ni);
     if (lane == 0) wave_sums[4 * blockIdx.x + wid] = make_ulonglong4(b1, b2, i1, i2);
   }
   if (counters) {
-    const unsigned long long nbd = wave_sum_u64(n_band), nrp = wave_sum_u64(n_replay);
+    const unsigned long long nbd = wave_sum_u64(px.n_rare & 0xffffu), nrp = wave_sum_u64(px.n_rare >> 16);
     if (lane == 0) {
       if (nbd) atomicAdd(&counters[2], nbd);
       if (nrp) atomicAdd(&counters[3], nrp);
