@@ -33,19 +33,21 @@ struct DeviceScene {
 // Per-Gaussian outputs of Preprocess
 // ---------------------------------------------------------------------------
 // Render record, 64 bytes, read by the blend kernel through the sorted ids.
-// The splatting opacity in the log2 domain is
-//   q(dx, dy) = qa dx^2 + qb dx dy + qc dy^2 + ql,   alpha = min(alpha_max, 2^q)
-// with (qa, qb, qc) = -(1/2) log2(e) (conic_a, 2 conic_b, conic_c) and
-// ql = log2(opacity); dx = x - i, dy = y - j for pixel (i, j).
+// The splatting opacity (Eq. 2) in the log2 domain, on the principal axes of
+// the conic:
+//   q = ql - a1 u^2 - a2 v^2,  u = rc dx - rs dy,  v = rs dx + rc dy,
+//   alpha = min(alpha_max, 2^q),
+// with ql = log2(opacity), (a1, a2) the eigenvalues of (log2(e) / 2) conic
+// and dx = x - i, dy = y - j for pixel (i, j).
 struct alignas(16) RenderRecord {
   uint32_t box_x;         // lo | hi << 16: pixel columns that may have alpha >= alpha_low
   uint32_t box_y;         // lo | hi << 16: pixel rows (lo > hi: none)
   uint32_t depth_key;     // bits of the fp32 view-space depth
-  uint32_t pad1;
+  float ql;
   double x, y;            // projected centre, pixel centres at integers
-  float qa, qb, qc, ql;
+  float rc, rs, a1, a2;
   float r, g, b;
-  uint32_t pad2;
+  float dq;               // bound on the FP32 error of q where it matters (+inf: decide in FP64)
 };
 static_assert(sizeof(RenderRecord) == 64, "render record is four 16-byte loads");
 
@@ -73,6 +75,7 @@ struct CullArgs {
   int32_t mode;
   int32_t quad_cull;        // render-side 8 x 8 quadrant cull in the culling modes
   double alpha_low;
+  double q_low;             // log2(alpha_low)
   double lowpass;
 };
 
@@ -80,9 +83,8 @@ struct BlendArgs {
   float alpha_max;
   float t_min;
   float q_low;              // log2(alpha_low) rounded to float
-  float q_band;             // half-width of the FP64 re-decision band on q
-  float q_cand;             // q_low - 2 q_band: entries below it cannot blend or enter the band
-  float t_band_lo, t_band_hi; // fp32 transmittances that trigger an FP64 replay
+  float band_floor;         // added to each Gaussian's exponent error bound (0: no FP64 bands)
+  float t_band;             // 1: FP64 transmittance replays near t_min, 0: none
   double alpha_low_d, alpha_max_d, t_min_d;
   float bg[3];
   int32_t lb_cap;

@@ -236,29 +236,24 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   cu.mode = p->cull;
   cu.quad_cull = (p->flags & ADR_FLAG_NO_QUAD_CULL) ? 0 : 1;
   cu.alpha_low = p->alpha_low;
+  cu.q_low = std::log2(p->alpha_low);
   cu.lowpass = p->lowpass;
 
   BlendArgs bl{};
   bl.alpha_max = (float)p->alpha_max;
   bl.t_min = (float)p->t_min;
   bl.q_low = (float)std::log2(p->alpha_low);
-  bl.q_band = 1.0f / 4096.0f;  // FP32 q carries ~1e-5 error; the band is >20x that
-  // FP32 transmittance drifts from FP64 by at most ~2e-5 relative per blend
-  // (alpha near 0.99 is the worst case); the band is ~50x a single blend's error
-  bl.t_band_lo = (float)(p->t_min * (1.0 - 1.0 / 1024.0));
-  bl.t_band_hi = (float)(p->t_min * (1.0 + 1.0 / 1024.0));
+  // FP64 bands: each Gaussian's exponent band is its error bound plus 2^-19
+  // (the rounding of log2(alpha_low) to float and of the comparison); the
+  // transmittance band follows a running error bound per pixel.
+  bl.exact = (p->flags & ADR_FLAG_NO_EXACT_BAND) ? 0 : 1;
+  bl.band_floor = bl.exact ? 0x1p-19f : 0.f;
+  bl.t_band = bl.exact ? 1.f : 0.f;
   bl.alpha_low_d = p->alpha_low;
   bl.alpha_max_d = p->alpha_max;
   bl.t_min_d = p->t_min;
   for (int c = 0; c < 3; ++c) bl.bg[c] = p->background[c];
   bl.lb_cap = p->lb_cap;
-  bl.exact = (p->flags & ADR_FLAG_NO_EXACT_BAND) ? 0 : 1;
-  if (!bl.exact) {  // empty bands: the FP32 decisions stand
-    bl.q_band = 0.f;
-    bl.t_band_lo = 1.f;
-    bl.t_band_hi = 0.f;
-  }
-  bl.q_cand = bl.q_low - 2.0f * bl.q_band;
 
   if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
   if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;

@@ -134,6 +134,60 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
   return v;
 }
 
+// Bound on the rounding error of the blend stage's FP32 exponent, evaluated
+// on the principal axes of the conic (no cancellation between its terms):
+//   u = fma(c, dx, -(s dy)),  v = fma(s, dx, c dy),
+//   q = fma(-(a1 u), u, fma(-(a2 v), v, ql)),  dx = fl(fl(x - qx0) - fx)
+// with the quadrant offset fx in [0, 7] and c, s, a1, a2, ql rounded from
+// FP64. First-order error analysis (unit roundoff u0 = 2^-24) gives, at a
+// pixel where P(d) = a1 u^2 + a2 v^2 = p,
+//   |q - q_exact| <= u0 [p (8 sqrt(2) (sqrt(a1) + sqrt(a2)) / sqrt(amin) + 6)
+//                        + 20 sqrt(p) (sqrt(a1) + sqrt(a2)) + 3 |ql|],
+// using |dx| + |dy| <= sqrt(2 p / amin). The bound returned (times 1.25) is
+// its value at p = pm, the largest P where q can reach
+// log2(alpha_low) - d0. Beyond pm the same bound must keep FP32 from lifting
+// q to the candidate threshold log2(alpha_low) - 2 band; if that cannot be
+// shown, or the bound exceeds 2^-8, the Gaussian is marked for FP64
+// decisions only (+inf).
+__device__ double exponent_error_bound(double a1, double a2, double ql, double q_low) {
+  const double u0 = 0x1p-24, d0 = 0.02, inf = __builtin_huge_val();
+  if (!(a1 > 0.0) || !(a2 > 0.0)) return inf;
+  const double ra = sqrt(a1) + sqrt(a2), amin = fmin(a1, a2);
+  const double k1 = 1.25 * u0 * (8.0 * 1.4142135623730951 * ra / sqrt(amin) + 6.0);
+  const double k2 = 1.25 * u0 * 20.0 * ra;
+  const double k0 = 1.25 * u0 * 3.0 * fabs(ql);
+  const double m = ql - q_low;  // q = q_low + m - P
+  const double pm = fmax(m + d0, 0.0);
+  const double dq = k1 * pm + k2 * sqrt(pm) + k0;
+  if (!(dq <= 0x1p-8)) return inf;
+  // For P = p >= pm: q_fp32 <= q_low + m - p + k1 p + k2 sqrt(p) + k0 must stay
+  // below the threshold: f(p) = (1 - k1) p - k2 sqrt(p) - m > 2 band + k0.
+  const double A = 1.0 - k1, B = k2;
+  if (!(A > 0.5)) return inf;
+  const double sp = sqrt(pm), sstar = B / (2.0 * A);
+  const double fmin_ = sp >= sstar ? A * pm - B * sp - m : -m - B * B / (4.0 * A);
+  const double band = dq + 0x1p-19;
+  if (!(fmin_ > 2.0 * band + k0 + 0x1p-19)) return inf;
+  return dq;
+}
+
+// Principal axes of P = h [[ca, cb], [cb, cc]], h = log2(e) / 2, by one
+// Jacobi rotation: P(d) = a1 u^2 + a2 v^2 with u = c dx - s dy, v = s dx + c dy.
+__device__ __forceinline__ void principal_axes(double ca, double cb, double cc, double& c, double& s, double& a1,
+                                               double& a2) {
+  const double h = 0.5 * 1.4426950408889634074;
+  const double pa = h * ca, pb = h * cb, pg = h * cc;
+  double t = 0.0;
+  if (pb != 0.0) {
+    const double tau = (pg - pa) / (2.0 * pb);
+    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  }
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+  a1 = pa - t * pb;
+  a2 = pg + t * pb;
+}
+
 __global__ void __launch_bounds__(256) preprocess_kernel(
     const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
     const float* __restrict__ planes, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, CullArgs cull,
@@ -247,21 +301,26 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
           const double vn = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
           float cr, cg, cbl;
           sh_colour(planes, n, g, n_coeff, shc, (float)(vx * vn), (float)(vy * vn), (float)(vz * vn), cr, cg, cbl);
-          const double nl2e = -0.5 * 1.4426950408889634074;  // -(1/2) log2(e)
+          double rc, rs, a1, a2;
+          principal_axes(ca, cb, cc, rc, rs, a1, a2);
+          const double ql = log2(op);
           RenderRecord rr;
           rr.x = x;
           rr.y = y;
-          rr.qa = (float)(nl2e * ca);
-          rr.qb = (float)(2.0 * nl2e * cb);
-          rr.qc = (float)(nl2e * cc);
-          rr.ql = (float)log2(op);
+          rr.rc = (float)rc;
+          rr.rs = (float)rs;
+          rr.a1 = (float)a1;
+          rr.a2 = (float)a2;
+          rr.ql = (float)ql;
           rr.r = cr;
           rr.g = cg;
           rr.b = cbl;
           rr.box_x = pack16(bx_lo, bx_hi);
           rr.box_y = pack16(by_lo, by_hi);
           rr.depth_key = dkey;
-          rr.pad1 = rr.pad2 = 0u;
+          // FP32 exponent error bound for the blend stage, rounded up
+          const double dq = exponent_error_bound(a1, a2, ql, cull.q_low);
+          rr.dq = dq > 1e30 ? __builtin_huge_valf() : (float)dq * (1.0f + 0x1p-20f);
           rec[g] = rr;
           ExactRecord er;
           er.ca = ca;

@@ -28,8 +28,8 @@ namespace adr {
 namespace {
 
 struct alignas(16) Staged {
-  float4 a;  // x - qx0, y - qy0, qa, qb
-  float4 b;  // qc, ql, r, g
+  float4 a;  // x - qx0, y - qy0, rc, rs
+  float4 b;  // a1, a2, ql, exponent band (the FP32 error bound + floor)
 };
 
 constexpr int kSub = 4;  // 4 x 4 pixel sub-blocks, 16 lanes each
@@ -77,25 +77,40 @@ __device__ __noinline__ double alpha_fp64_at(const RenderRecord* __restrict__ re
   return alpha_fp64(exact[g], rec[g].x, rec[g].y, pi, pj, alpha_max);
 }
 
-// log2-domain exponent of a staged Gaussian at the lane's pixel (lx, ly)
+// log2-domain exponent of a staged Gaussian at the lane's pixel (lx, ly),
+// on its principal axes: every term has the sign of its sum.
 __device__ __forceinline__ float quad_form(const float4& A, const float4& B, float fx, float fy) {
   const float dx = A.x - fx, dy = A.y - fy;
-  return fmaf(A.z * dx, dx, fmaf(A.w * dx, dy, fmaf(B.x * dy, dy, B.y)));
+  const float u = fmaf(A.z, dx, -(A.w * dy));
+  const float v = fmaf(A.w, dx, A.z * dy);
+  return fmaf(-(B.x * u), u, fmaf(-(B.y * v), v, B.z));
 }
 
 // FP64 transmittance of pixel (ri, rj) after list entries [s, k_now]: the
 // wave's lanes take every 64th entry and the partial products are combined.
+// A lane's id loads run two entries ahead and its box loads one entry ahead
+// (clamped to the range, so none waits on a branch); its product runs over
+// its entries in list order.
 __device__ __noinline__ double replay_fp64(const RenderRecord* __restrict__ rec,
                                            const ExactRecord* __restrict__ exact,
                                            const uint32_t* __restrict__ vals, uint32_t n_gauss, uint32_t s,
                                            uint32_t k_now, int ri, int rj, int lane, const BlendArgs& bl) {
   double prod = 1.0;
-  for (uint32_t kk = s + lane; kk <= k_now; kk += 64) {
-    const uint32_t gg = min(vals[kk], n_gauss - 1);
-    const RenderRecord& rr = rec[gg];
-    if (!box_has(rr.box_x, rr.box_y, ri, rj)) continue;
-    const double ad = alpha_fp64(exact[gg], rr.x, rr.y, ri, rj, bl.alpha_max_d);
-    if (ad >= bl.alpha_low_d) prod *= 1.0 - ad;
+  uint64_t kk = (uint64_t)s + lane;
+  const uint64_t kl = k_now;
+  uint32_t g = min(vals[min(kk, kl)], n_gauss - 1);
+  uint32_t g_n = min(vals[min(kk + 64, kl)], n_gauss - 1);
+  uint2 bx = *reinterpret_cast<const uint2*>(&rec[g].box_x);
+  for (; kk <= kl; kk += 64) {
+    const uint2 bx_n = *reinterpret_cast<const uint2*>(&rec[g_n].box_x);
+    const uint32_t raw_nn = vals[min(kk + 128, kl)];
+    if (box_has(bx.x, bx.y, ri, rj)) {
+      const double ad = alpha_fp64(exact[g], rec[g].x, rec[g].y, ri, rj, bl.alpha_max_d);
+      if (ad >= bl.alpha_low_d) prod *= 1.0 - ad;
+    }
+    g = g_n;
+    bx = bx_n;
+    g_n = min(raw_nn, n_gauss - 1);
   }
   return wave_prod_f64(prod);
 }
@@ -142,12 +157,13 @@ __device__ __forceinline__ SubMasks sub_masks(uint2 box, int qx0, int qy0) {
   return s;
 }
 
-// The part of a render record the blend stages (centre, exponent
-// coefficients, colour), loaded one batch ahead of its use.
+// The part of a render record the batch staging needs (centre, exponent
+// coefficients, error bound), loaded one batch ahead of its use.
 struct Fetched {
   double x, y;
-  float4 q;
-  float r, g, b;
+  float4 q;  // rc, rs, a1, a2
+  float ql;
+  float dq;  // exponent error bound
 };
 
 __device__ __forceinline__ Fetched fetch(const RenderRecord* __restrict__ rec, uint32_t g) {
@@ -155,11 +171,9 @@ __device__ __forceinline__ Fetched fetch(const RenderRecord* __restrict__ rec, u
   Fetched f;
   f.x = r.x;
   f.y = r.y;
-  f.q = *reinterpret_cast<const float4*>(&r.qa);
-  const float4 c = *reinterpret_cast<const float4*>(&r.r);
-  f.r = c.x;
-  f.g = c.y;
-  f.b = c.z;
+  f.q = *reinterpret_cast<const float4*>(&r.rc);
+  f.ql = r.ql;
+  f.dq = r.dq;
   return f;
 }
 
@@ -202,44 +216,54 @@ __global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __rest
 // Per-pixel blend state (Eqs. 2-3) and its load counters.
 struct Pixel {
   float T, cr, cg, cb;
+  float E;          // bound on the relative error of T against its FP64 value
   uint32_t nb;      // blended entries (l_blend)
   uint32_t stop_k;  // list position of the entry that stopped the pixel
   uint32_t n_rare;   // FP64 re-decisions (low 16 bits) and replays (high 16 bits)
   bool done;
 };
 
-// One front-to-back blend of a staged Gaussian (A, B, C) at the lane's
-// pixel: alpha from the FP32 exponent, re-decided in FP64 near
-// log2(alpha_low); the transmittance recomputed in FP64 by the whole wave
-// when it lands near t_min. Every lane of the wave must call it.
-__device__ __forceinline__ void blend_step(Pixel& px, const float4& A, const float4& B, float blue, int slot,
+// One front-to-back blend of a staged Gaussian (A, B, colour cols[slot]) at the
+// lane's pixel. The FP32 exponent decides alpha >= alpha_low unless it lies
+// within the Gaussian's error band of log2(alpha_low), where FP64 decides.
+// E bounds the relative error of the FP32 transmittance: each blend adds
+// alpha / (1 - alpha) times alpha's relative error (the exponent bound times
+// ln 2, plus the exp2 and rounding error) and one rounding. When T lands
+// within that bound (times 1.5) of t_min, the whole wave recomputes the
+// pixel's transmittance in FP64 over the list so far. Every lane of the wave
+// must call it.
+__device__ __forceinline__ void blend_step(Pixel& px, const float4& A, const float4& B, const float4* cols, int slot,
                                            uint32_t base, const uint32_t* gids, float fx, float fy, int pi, int pj,
                                            int lane, uint32_t cap, uint32_t s,
                                            const RenderRecord* __restrict__ rec,
                                            const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
                                            uint32_t n_gauss, const BlendArgs& bl) {
+  const float4 col = cols[slot];  // read now, used at the end of the step
   const float q = quad_form(A, B, fx, fy);
   const float e2 = __builtin_amdgcn_exp2f(q);
   const bool live = !px.done;
   float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
   bool blend = live & (q >= bl.q_low);
-  const bool near_low = live & (fabsf(q - bl.q_low) < bl.q_band);
+  const bool near_low = live & (fabsf(q - bl.q_low) < B.w);
   float af = blend ? a : 0.f;
   float Tn = fmaf(-af, px.T, px.T);  // T (1 - alpha) with one rounding
-  bool near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
+  const float rel = fmaf(B.w, 0.7f, 0x1p-20f);  // relative error of alpha: band * ln 2 (rounded up) + exp2
+  float En = px.E + (blend ? fmaf(af * __builtin_amdgcn_rcpf(1.f - af), rel, 0x1p-23f) : 0.f);
+  bool near_t = blend & (fabsf(Tn - bl.t_min) < bl.t_min * fmaf(1.5f, En, 0x1p-21f) * bl.t_band);
   float t_exact = 0.f;
   bool stop_exact = false;
   if (__builtin_expect(__ballot(near_low | near_t) != 0, 0)) {
-    // Rare (wave-uniform branch): an exponent near log2(alpha_low) is
-    // decided in FP64; a transmittance near t_min is recomputed in FP64 by
-    // the whole wave over the list so far.
+    // Rare (wave-uniform branch): an exponent within its band of
+    // log2(alpha_low) is decided in FP64; a transmittance near t_min is
+    // recomputed in FP64 by the whole wave over the list so far.
     if (near_low) {
       const double ad = alpha_fp64_at(rec, exact, gids[slot], pi, pj, bl.alpha_max_d);
       blend = ad >= bl.alpha_low_d;
       a = (float)ad;
       af = blend ? a : 0.f;
       Tn = fmaf(-af, px.T, px.T);
-      near_t = blend & (Tn >= bl.t_band_lo) & (Tn <= bl.t_band_hi);
+      En = px.E + (blend ? fmaf(af * __builtin_amdgcn_rcpf(1.f - af), 0x1p-23f, 0x1p-23f) : 0.f);
+      near_t = blend & (fabsf(Tn - bl.t_min) < bl.t_min * fmaf(1.5f, En, 0x1p-21f) * bl.t_band);
       px.n_rare += 1u;
     }
     uint64_t rm = __ballot(near_t);
@@ -257,10 +281,11 @@ __device__ __forceinline__ void blend_step(Pixel& px, const float4& A, const flo
     }
   }
   const float w = af * px.T;
-  px.cr = fmaf(B.z, w, px.cr);
-  px.cg = fmaf(B.w, w, px.cg);
-  px.cb = fmaf(blue, w, px.cb);
+  px.cr = fmaf(col.x, w, px.cr);
+  px.cg = fmaf(col.y, w, px.cg);
+  px.cb = fmaf(col.z, w, px.cb);
   px.T = near_t ? t_exact : Tn;
+  px.E = near_t ? 0x1p-24f : En;  // after a replay only the rounding to float remains
   px.nb += blend ? 1u : 0u;
   // bitwise on purpose: no short-circuit branches in the common path
   const bool t_stop = near_t ? stop_exact : (px.T < bl.t_min);
@@ -269,16 +294,16 @@ __device__ __forceinline__ void blend_step(Pixel& px, const float4& A, const flo
   px.done = px.done | stop;
 }
 
-__global__ void __launch_bounds__(256) render_kernel(
+__global__ void __launch_bounds__(256, 4) render_kernel(
     const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, uint32_t n_pairs, uint32_t n_gauss,
     CamArgs cam, BlendArgs bl, int n_tiles, float* __restrict__ image, float* __restrict__ final_t,
     uint32_t* __restrict__ l_iter, uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums,
     unsigned long long* __restrict__ counters) {
   // per wave, per batch slot (= list position - batch start): the staged
-  // record, its blue and its Gaussian id; slot 64 is a null record
+  // record, its colour and its Gaussian id; slot 64 is a null record
   __shared__ Staged stage[4][65];
-  __shared__ float stage_blue[4][65];
+  __shared__ float4 stage_col[4][65];
   __shared__ uint32_t stage_gid[4][65];
   const int tile = (int)min(order[blockIdx.x], (uint32_t)(n_tiles - 1));
   const int W = cam.width, H = cam.height;
@@ -297,14 +322,14 @@ __global__ void __launch_bounds__(256) render_kernel(
   const bool inside = pi < W && pj < H;
   const float fx = (float)lx, fy = (float)ly;
   Staged* my = stage[wid];
-  float* my_blue = stage_blue[wid];
+  float4* my_col = stage_col[wid];
   uint32_t* my_gid = stage_gid[wid];
   if (lane == 0) {  // exponent -1e30: alpha 0, colour 0; evaluating it changes nothing
     Staged z;
     z.a = make_float4(0.f, 0.f, 0.f, 0.f);
-    z.b = make_float4(0.f, -1e30f, 0.f, 0.f);
+    z.b = make_float4(0.f, 0.f, -1e30f, 0.f);  // q = -1e30 and band 0: never a candidate
     my[64] = z;
-    my_blue[64] = 0.f;
+    my_col[64] = make_float4(0.f, 0.f, 0.f, 0.f);
     my_gid[64] = 0u;
   }
 
@@ -314,6 +339,7 @@ __global__ void __launch_bounds__(256) render_kernel(
   const uint32_t s = min(ranges[2 * tile], e);
   Pixel px;
   px.T = 1.f;
+  px.E = 0.f;
   px.cr = px.cg = px.cb = 0.f;
   px.nb = 0;
   px.stop_k = 0xffffffffu;
@@ -350,11 +376,13 @@ __global__ void __launch_bounds__(256) render_kernel(
     if ((any >> lane) & 1ull) {
       Staged st;
       st.a = make_float4((float)(f_b.x - (double)qx0), (float)(f_b.y - (double)qy0), f_b.q.x, f_b.q.y);
-      st.b = make_float4(f_b.q.z, f_b.q.w, f_b.r, f_b.g);
+      const float band = bl.exact ? f_b.dq + bl.band_floor : 0.f;
+      st.b = make_float4(f_b.q.z, f_b.q.w, f_b.ql, band);
       my[lane] = st;
-      my_blue[lane] = f_b.b;
       my_gid[lane] = g_b;
     }
+    // colours are needed only by phase 2: their load overlaps phase 1
+    const float4 col_b = *reinterpret_cast<const float4*>(&rec[((any >> lane) & 1ull) ? g_b : 0u].r);
     // the sub-block's entries of this batch, in list order: the set bits
     uint64_t my_mask = sb == 0 ? hm.m[0] : sb == 1 ? hm.m[1] : sb == 2 ? hm.m[2] : hm.m[3];
     const int n_iter = max(max(__popcll(hm.m[0]), __popcll(hm.m[1])), max(__popcll(hm.m[2]), __popcll(hm.m[3])));
@@ -372,7 +400,7 @@ __global__ void __launch_bounds__(256) render_kernel(
 
     // Phase 1, candidates: the 16 lanes of a sub-block step through its
     // entries (lowest set bit first) and mark, per pixel, the batch slots
-    // whose exponent reaches log2(alpha_low) less a margin twice the FP64
+    // whose exponent reaches log2(alpha_low) less twice the Gaussian's
     // band. No step depends on the previous one; two register sets alternate
     // so that each record is read from LDS one step before its use. Every
     // unmarked entry has alpha < alpha_low at this pixel in FP32 and lies
@@ -390,7 +418,7 @@ __global__ void __launch_bounds__(256) render_kernel(
         B1 = my[s1].b;
         __builtin_amdgcn_sched_barrier(0);  // issue the reads here, one step before their use
         float q = quad_form(A0, B0, fx, fy);
-        cand |= (q >= bl.q_cand && s0 < 64) ? (1ull << (s0 & 63)) : 0ull;
+        cand |= (q >= fmaf(-2.f, B0.w, bl.q_low) && s0 < 64) ? (1ull << (s0 & 63)) : 0ull;
         s0 = next_slot(my_mask);
         __builtin_amdgcn_sched_barrier(0);  // the step above completes before the wait below
         ready(A1);
@@ -399,13 +427,17 @@ __global__ void __launch_bounds__(256) render_kernel(
         B0 = my[s0].b;
         __builtin_amdgcn_sched_barrier(0);
         q = quad_form(A1, B1, fx, fy);
-        cand |= (q >= bl.q_cand && s1 < 64) ? (1ull << (s1 & 63)) : 0ull;
+        cand |= (q >= fmaf(-2.f, B1.w, bl.q_low) && s1 < 64) ? (1ull << (s1 & 63)) : 0ull;
         s1 = next_slot(my_mask);
         __builtin_amdgcn_sched_barrier(0);
         ready(A0);
         ready(B0);
       }
     }
+    if ((any >> lane) & 1ull) my_col[lane] = col_b;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // Phase 2, blending: each lane walks its candidates in slot order, which
     // is list (depth) order, with the exact decision logic; two register
     // sets alternate as above. The wave steps while any lane has candidates
@@ -414,17 +446,14 @@ __global__ void __launch_bounds__(256) render_kernel(
       uint64_t cm = px.done ? 0ull : cand;
       int s0 = next_slot(cm), s1 = next_slot(cm);
       float4 A0 = my[s0].a, B0 = my[s0].b, A1, B1;
-      float b0 = my_blue[s0], b1;
       ready(A0);
       ready(B0);
-      ready(b0);
 #pragma unroll 1
       while (__ballot(s0 != 64) != 0) {
         A1 = my[s1].a;
         B1 = my[s1].b;
-        b1 = my_blue[s1];
         __builtin_amdgcn_sched_barrier(0);
-        blend_step(px, A0, B0, b0, s0, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
+        blend_step(px, A0, B0, my_col, s0, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
         if (px.done) {
           cm = 0;
           s1 = 64;
@@ -433,13 +462,11 @@ __global__ void __launch_bounds__(256) render_kernel(
         __builtin_amdgcn_sched_barrier(0);
         ready(A1);
         ready(B1);
-        ready(b1);
         if (__ballot(s1 != 64) == 0) break;
         A0 = my[s0].a;
         B0 = my[s0].b;
-        b0 = my_blue[s0];
         __builtin_amdgcn_sched_barrier(0);
-        blend_step(px, A1, B1, b1, s1, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
+        blend_step(px, A1, B1, my_col, s1, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
         if (px.done) {
           cm = 0;
           s0 = 64;
@@ -448,8 +475,7 @@ __global__ void __launch_bounds__(256) render_kernel(
         __builtin_amdgcn_sched_barrier(0);
         ready(A0);
         ready(B0);
-        ready(b0);
-      }
+        }
     }
     if (__ballot(!px.done) == 0) goto finished;
     __builtin_amdgcn_wave_barrier();  // all reads of this batch's slots before the next writes
