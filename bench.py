@@ -85,6 +85,39 @@ def algorithmic_bytes(stage, n, n_vis, n_pairs, n_pix, n_tiles, n_coeff, depth_b
     return 0
 
 
+KERNEL_SOURCES = {"render_kernel": ("paper_2409_08669_amd/csrc/render.hip", "paper_2409_08669_amd/csrc/adr_internal.h")}
+TRAFFIC_PROFILE = "profiles/hbm_traffic_1M_1080p_aabb.md"
+
+
+def source_digest(kernel):
+    """sha256 over the source files a kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, ()):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE and WRITE_SIZE passes,
+    scaled by a plain copy) from the committed counter summary of the AABB
+    headline frame, or None when the kernel's sources changed since the
+    counters were taken (the summary records their digest) or it has no row."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    digest, row = None, None
+    for line in open(path):
+        if line.startswith(f"Source digest of {kernel}:"):
+            digest = line.split("`")[1] if line.count("`") >= 2 else None
+        if line.startswith(f"| {kernel} "):
+            row = [c.strip() for c in line.strip().strip("|").split("|")]
+    if digest != source_digest(kernel) or row is None:
+        return None
+    return int(round((float(row[-2]) + float(row[-1])) * 1e6))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -192,7 +225,7 @@ def main():
         achieved = flops / (kern[dom] * 1e-3) / 1e12
         roofline = {"kernel": "render_kernel", "bound": "alu", "achieved": round(achieved, 3),
                     "peak": round(VALU_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
-                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": None,
+                    "frac": round(achieved / VALU_PEAK_TFLOPS, 4), "traffic": measured_traffic("render_kernel"),
                     "algorithmic_flops": int(flops), "examined": head["sum_iter"], "blended": head["sum_blend"],
                     "avg_ms": round(kern[dom], 4)}
     else:

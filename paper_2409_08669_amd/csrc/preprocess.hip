@@ -143,7 +143,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 // pixel where P(d) = a1 u^2 + a2 v^2 = p,
 //   |q - q_exact| <= u0 [p (8 sqrt(2) (sqrt(a1) + sqrt(a2)) / sqrt(amin) + 6)
 //                        + 20 sqrt(p) (sqrt(a1) + sqrt(a2)) + 3 |ql|],
-// using |dx| + |dy| <= sqrt(2 p / amin). The bound returned (times 1.25) is
+// using |dx| + |dy| <= sqrt(2 p / amin). The bound returned (times 1.5) is
 // its value at p = pm, the largest P where q can reach
 // log2(alpha_low) - d0. Beyond pm the same bound must keep FP32 from lifting
 // q to the candidate threshold log2(alpha_low) - 2 band; if that cannot be
@@ -153,9 +153,9 @@ __device__ double exponent_error_bound(double a1, double a2, double ql, double q
   const double u0 = 0x1p-24, d0 = 0.02, inf = __builtin_huge_val();
   if (!(a1 > 0.0) || !(a2 > 0.0)) return inf;
   const double ra = sqrt(a1) + sqrt(a2), amin = fmin(a1, a2);
-  const double k1 = 1.25 * u0 * (8.0 * 1.4142135623730951 * ra / sqrt(amin) + 6.0);
-  const double k2 = 1.25 * u0 * 20.0 * ra;
-  const double k0 = 1.25 * u0 * 3.0 * fabs(ql);
+  const double k1 = 1.5 * u0 * (8.0 * 1.4142135623730951 * ra / sqrt(amin) + 6.0);
+  const double k2 = 1.5 * u0 * 20.0 * ra;
+  const double k0 = 1.5 * u0 * 3.0 * fabs(ql);
   const double m = ql - q_low;  // q = q_low + m - P
   const double pm = fmax(m + d0, 0.0);
   const double dq = k1 * pm + k2 * sqrt(pm) + k0;

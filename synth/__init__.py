@@ -8,6 +8,7 @@ from .scenes import (  # noqa: F401
     Scene,
     Camera,
     scene_small,
+    scene_needles,
     scene_clusters,
     scene_heavy,
     camera_pinhole,

@@ -77,6 +77,22 @@ def scene_small(n: int = 2000, seed: int = 0) -> Scene:
     return Scene(_f32(means), _f32(log_scales), _f32(quats), _f32(logits), _f32(sh), 0)
 
 
+def scene_needles(n: int = 1500, seed: int = 0) -> Scene:
+    """Stress scene for the FP32 precision of the blend: means U[-1,1]^3,
+    one log-scale N(-1.5,0.5) and two N(-6,0.7) per Gaussian (axis ratios
+    ~10^2 to 10^3, so projected footprints are long thin needles at every
+    angle), random quaternions, opacity logits N(1,2), rgb ~ U[0,1]."""
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, size=(n, 3))
+    log_scales = rng.normal(-6.0, 0.7, size=(n, 3))
+    log_scales[np.arange(n), rng.integers(0, 3, size=n)] = rng.normal(-1.5, 0.5, size=n)
+    quats = rng.normal(0.0, 1.0, size=(n, 4))
+    logits = rng.normal(1.0, 2.0, size=(n,))
+    rgb = rng.uniform(0.0, 1.0, size=(n, 3))
+    sh = ((rgb - 0.5) / _Y00).reshape(n, 1, 3)
+    return Scene(_f32(means), _f32(log_scales), _f32(quats), _f32(logits), _f32(sh), 0)
+
+
 def _cluster_means(rng, n, n_clusters, box, std_lo, std_hi, log_uniform):
     centers = rng.uniform(-box, box, size=(n_clusters, 3))
     if log_uniform:

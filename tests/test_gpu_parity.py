@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from synth import (Camera, scene_small, scene_clusters, camera_small, camera_orbit, camera_1080p)
+from synth import (Camera, scene_small, scene_needles, scene_clusters, camera_small, camera_orbit, camera_1080p)
 
 pytestmark = pytest.mark.gpu
 
@@ -98,6 +98,20 @@ def test_small_scene_parity(P, ws, small, mode):
     s, sg, cam = small
     say(f"small scene 2000 G, 128x128, mode {mode}")
     g = gpu_frame(P, ws, sg, cam, mode)
+    o = O.render_frame(s, cam, oracle_params(mode))
+    check_integer_stage(g, o, s.n)
+    check_pixels(g, o)
+    check_load_sums(g, o)
+
+
+@pytest.mark.parametrize("mode", [0, 2], ids=["3sigma", "aabb"])
+def test_needle_scene_parity(P, ws, mode):
+    """Long thin Gaussians at every angle (projected axis ratios up to ~2600):
+    the FP32 exponent's error bounds must keep every decision exact."""
+    s = scene_needles(1500, seed=2)
+    cam = camera_small(128, 128)
+    say(f"needle scene 1500 G, 128x128, mode {mode}")
+    g = gpu_frame(P, ws, P.Scene.from_synth(s), cam, mode)
     o = O.render_frame(s, cam, oracle_params(mode))
     check_integer_stage(g, o, s.n)
     check_pixels(g, o)
