@@ -172,11 +172,11 @@ def main():
         dt = time.perf_counter() - t0
         # Stage durations: the same frames again with HIP events around every
         # stage, recorded on the library's stream, read after each frame.
-        stage_sum = {s: 0.0 for s in STAGES}
+        stage_runs = {s: [] for s in STAGES}
         for _ in range(args.steps):
             P.render(sg, cam, timed, ws, **out)
             for k, v in ws.stage_times().items():
-                stage_sum[k] += v
+                stage_runs[k].append(v)
         torch.cuda.synchronize()
         counters = ws.counters()
         sums = out["load_sums"].cpu().numpy()
@@ -185,10 +185,23 @@ def main():
         results[name] = dict(
             fps=args.steps / dt, ms_per_frame=1e3 * dt / args.steps, pairs=int(n_pairs),
             sum_blend=int(sums[0]), sum_iter=int(sums[2]),
-            visible=counters.get("visible"), depth_bits=counters.get("depth_sort_bits"), stages_ms={k: v / args.steps for k, v in stage_sum.items()},
+            visible=counters.get("visible"), depth_bits=counters.get("depth_sort_bits"),
+            stages_ms={k: float(np.mean(v)) for k, v in stage_runs.items()},
+            stages_ms_pctl={k: [round(float(x), 4) for x in np.percentile(v, [10, 50, 90])]
+                            for k, v in stage_runs.items()},
             band_redecisions=counters.get("band_redecisions"), t_replays=counters.get("t_replays"),
             load_mean_blend=mean_b, load_std_blend=std_b, load_mean_iter=mean_i, load_std_iter=std_i)
         images[name] = out["image"].clone()
+        if name == "aabb":
+            # Load imbalance of the paper's pixel-parallel blend: every wave
+            # (8 x 8 pixels) runs as long as its longest pixel list, so its
+            # executed work is 64 x max l_iter against the sum of l_iter.
+            li = out["l_iter"].cpu().numpy().astype(np.int64)
+            hp, wp = -(-h // 8) * 8, -(-w // 8) * 8
+            pad = np.zeros((hp, wp), dtype=np.int64)
+            pad[:h, :w] = li
+            wave_max = pad.reshape(hp // 8, 8, wp // 8, 8).max(axis=(1, 3))
+            results[name]["load_imbalance_E_exec_over_E_alg"] = round(float(64 * wave_max.sum() / max(li.sum(), 1)), 4)
         log(f"mode {name}: {results[name]['fps']:.1f} frames/s, pairs {n_pairs}, stages "
             + ", ".join(f"{k} {v:.3f}" for k, v in results[name]["stages_ms"].items()))
     first = next(iter(images.values()))
@@ -200,6 +213,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+    # Measured device copy bandwidth (512 MiB read + 512 MiB written per copy),
+    # the practical HBM ceiling the stage fractions are also quoted against.
+    copy_gbs = None
+    if not args.only:
+        src = torch.ones(128 << 20, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del src, dst
     if args.only:
         r = results[args.only]
         print(json.dumps({"mode": args.only, "fps": round(r["fps"], 2), "pairs": r["pairs"],
@@ -219,7 +248,9 @@ def main():
         b = algorithmic_bytes(s_, args.n, n_vis, head["pairs"], w * h, n_tiles, 16, head["depth_bits"] or 32)
         per_stage[s_] = {"ms": round(ms, 4), "algorithmic_bytes": int(b),
                          "GB/s": round(b / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
-                         "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+                         "frac_hbm": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None,
+                         "frac_copy": round(b / (ms * 1e-3) / 1e9 / copy_gbs, 4) if ms > 0 and copy_gbs else None,
+                         "ms_p10_p50_p90": head["stages_ms_pctl"][s_]}
     if dom == "render":
         flops = FLOPS_PER_EXAMINED * head["sum_iter"] + FLOPS_PER_BLENDED * head["sum_blend"]
         achieved = flops / (kern[dom] * 1e-3) / 1e12
@@ -265,6 +296,8 @@ def main():
         "speedup_adaptive_vs_3sigma": round(results["adaptive"]["fps"] / results["3sigma"]["fps"], 4),
         "identical_output_across_modes": identical,
         "stages": per_stage,
+        "hbm_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
+        "load_imbalance_E_exec_over_E_alg": results["aabb"].get("load_imbalance_E_exec_over_E_alg"),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving_p99_ms": None,

@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from synth import (Camera, scene_small, scene_needles, scene_clusters, camera_small, camera_orbit, camera_1080p)
+from synth import (Camera, scene_small, scene_needles, scene_clusters, scene_heavy, camera_small, camera_orbit,
+                   camera_1080p, cameras_sweep)
 
 pytestmark = pytest.mark.gpu
 
@@ -262,3 +263,38 @@ def test_headline_scale_integer_stage_and_sampled_tiles(P, ws):
     b = gpu_frame(P, ws, sg, cam, 2, debug=False)
     np.testing.assert_array_equal(a["image"], b["image"])
     np.testing.assert_array_equal(a["l_blend"], b["l_blend"])
+
+
+@pytest.mark.slow
+def test_load_imbalanced_scene_exact_and_capped(P, ws):
+    """3M Gaussians with 20% in 8 dense clusters, 1600x1040, first pose of the
+    32-pose sweep (tile lists up to ~76k entries): the AABB integer stage
+    bit-exact, then the exact and the capped blend on 40 sampled tiles (the 8
+    heaviest and 32 seeded). The cap is K = ceil(mean + 2 std) of l_blend over
+    the covered pixels of the oracle's sampled tiles."""
+    s = scene_heavy(3_000_000, seed=0)
+    cam = cameras_sweep(32)[0]
+    sg = P.Scene.from_synth(s)
+    pre = O.preprocess(s, cam, O.Params())
+    params = oracle_params(2)
+    rects = O.tile_rects(pre, cam, params)
+    keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+    ranges = O.tile_ranges(keys, cam)
+    say("3M G 1600x1040 AABB exact")
+    g = gpu_frame(P, ws, sg, cam, 2)
+    o = dict(tiles_touched=rects["tiles_touched"], n_pairs=int(keys.size), keys=keys, values=values, ranges=ranges)
+    check_integer_stage(g, o, s.n)
+    tx_n, ty_n = O.n_tiles(cam)
+    rng = np.random.default_rng(12)
+    busy = np.argsort(ranges[:, 1] - ranges[:, 0])[-8:]
+    tiles = np.unique(np.concatenate([rng.choice(tx_n * ty_n, 32, replace=False), busy]))
+    r = O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+    check_pixels(g, r, mask=r["done"])
+    covered = r["done"] & (r["l_blend"] > 0)
+    lb = r["l_blend"][covered].astype(np.float64)
+    k = int(math.ceil(lb.mean() + 2.0 * lb.std()))
+    say(f"  pairs {g['n_pairs']}  cap K = {k}")
+    gc = gpu_frame(P, ws, sg, cam, 2, lb_cap=k)
+    rc = O.render_image(pre, values, ranges, cam, oracle_params(2, lb_cap=k), tiles=tiles)
+    check_pixels(gc, rc, mask=rc["done"])
+    assert gc["l_blend"].max() <= k
