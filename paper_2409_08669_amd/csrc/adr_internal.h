@@ -114,6 +114,7 @@ struct adr_workspace {
   uint2* tile_rect = nullptr;      // (tx_lo | tx_hi << 16, ty_lo | ty_hi << 16)
   uint32_t* touched = nullptr;
   uint32_t* offsets = nullptr;     // inclusive sum of touched in depth order
+  uint32_t* touched_sorted = nullptr;  // tiles_touched in depth order
   adr::SortBuffers depth;          // (depth key, id) of every Gaussian, sorted by depth
   uint32_t* scan_partials = nullptr;
   int64_t scan_partials_capacity = 0;
@@ -128,6 +129,8 @@ struct adr_workspace {
   int64_t ranges_capacity = 0;
   uint32_t* tile_order = nullptr;  // render order of the tiles, longest lists first
   int64_t tile_order_capacity = 0;
+  uint32_t* order_counts = nullptr;  // per-block bucket counts of the tile order
+  int64_t order_counts_capacity = 0;
   // per frame: counters and the two sort histograms, zeroed (with the tile
   // ranges and the caller's load sums) by one kernel at the start of the frame
   unsigned long long* dev_counters = nullptr;  // kCounterSlots u64, see below
@@ -178,21 +181,23 @@ hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_
 int64_t preprocess_blocks(int64_t n);
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
                              hipStream_t stream);
-hipError_t launch_inclusive_sum(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
-                                uint32_t* partials, hipStream_t stream);
+hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
+                                hipStream_t stream);
 int64_t inclusive_sum_partials(int64_t n);
 hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint2* tile_rect, int64_t n_vis,
                             int64_t n_pairs, int32_t tiles_x, uint32_t* tile_keys, uint32_t* vals,
                             hipStream_t stream);
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
                              uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
-                             hipStream_t stream);
+                             hipStream_t stream, const uint32_t* gather_src = nullptr,
+                             uint32_t* gather_dst = nullptr);
 int64_t sort_scratch_entries(int64_t n);
 hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);
 hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, const RenderRecord* rec,
                                int64_t n_pairs, uint64_t* keys, hipStream_t stream);
-hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order,
+int64_t tile_order_scratch(int n_tiles);
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order, uint32_t* counts,
                              hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
                          const uint32_t* ranges, const uint32_t* order, int64_t n_pairs, int64_t n_gauss,

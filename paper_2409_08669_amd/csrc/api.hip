@@ -66,7 +66,9 @@ adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
     if ((st = grow(ws->tile_rect, c[2], n, "tile rects")) != ADR_OK) return st;
     if ((st = grow(ws->touched, c[3], n, "tiles_touched")) != ADR_OK) return st;
     if ((st = grow(ws->offsets, c5, n, "offsets")) != ADR_OK) return st;
-    int64_t m = c5;
+    int64_t c6 = ws->gauss_capacity;
+    if ((st = grow(ws->touched_sorted, c6, n, "tiles_touched in depth order")) != ADR_OK) return st;
+    int64_t m = c5 < c6 ? c5 : c6;
     for (int i = 0; i < 4; ++i) m = c[i] < m ? c[i] : m;
     ws->gauss_capacity = m;
   }
@@ -96,10 +98,10 @@ int bits_for(int64_t v) {
 using namespace adr;
 
 static void free_workspace_buffers(adr_workspace* ws) {
-  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->depth.keys[0],
+  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->touched_sorted, ws->depth.keys[0],
                   ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
                   ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->sort_scratch, ws->ranges,
-                  ws->tile_order, ws->wave_sums, ws->dev_counters, ws->hists, ws->block_parts};
+                  ws->tile_order, ws->order_counts, ws->wave_sums, ws->dev_counters, ws->hists, ws->block_parts};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (ws->host_counters) (void)hipHostFree(ws->host_counters);
@@ -258,6 +260,9 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
   if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;
   if ((st = grow(ws->tile_order, ws->tile_order_capacity, n_tiles, "tile order")) != ADR_OK) return st;
+  if ((st = grow(ws->order_counts, ws->order_counts_capacity, tile_order_scratch((int)n_tiles), "tile order counts")) !=
+      ADR_OK)
+    return st;
   if ((st = grow(ws->wave_sums, ws->wave_sums_capacity, 16 * n_tiles, "load-sum partials")) != ADR_OK) return st;
   const bool timing = (p->flags & ADR_FLAG_TIMING) != 0;
   ws->timing_valid = false;
@@ -320,13 +325,16 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     if (dbits > 32) dbits = 32;
     ws->last_depth_bits = dbits;
     const uint32_t lim = dbits >= 32 ? 0xffffffffu : (uint32_t)((1ull << dbits) - 1);
+    // the last pass also lays tiles_touched out in depth order for the scan
     ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, dbits, (uint32_t)dmin, lim, ws->sort_scratch,
-                              ws->hists, &dsorted, stream));
+                              ws->hists, &dsorted, stream, ws->touched, ws->touched_sorted));
+    if (s.n == 1)  // nothing to sort: the one Gaussian is its own order
+      ADR_HIP(hipMemcpyAsync(ws->touched_sorted, ws->touched, sizeof(uint32_t), hipMemcpyDeviceToDevice, stream));
   }
   const uint32_t* order = ws->depth.vals[dsorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
   // Stage 2: InclusiveSum of tiles_touched over the Gaussians in depth order
-  ADR_HIP(launch_inclusive_sum(ws->touched, order, ws->offsets, n_vis, ws->scan_partials, stream));
+  ADR_HIP(launch_inclusive_sum(ws->touched_sorted, ws->offsets, n_vis, ws->scan_partials, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[4], stream));
   // Stage 3: DuplicateWithKeys, in depth order, keyed by tile id
   ADR_HIP(launch_duplicate(ws->offsets, order, ws->tile_rect, n_vis, n_pairs, ca.tiles_x, ws->pairs.keys[0],
@@ -343,7 +351,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ADR_HIP(launch_tile_ranges(tiles, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[7], stream));
   // Stage 6: Render (tile order, blend, load sums)
-  ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, stream));
+  ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, ws->order_counts, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
   ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, n_pairs, s.n, ca, bl, out, ws,
                         stream));

@@ -184,32 +184,87 @@ __device__ __forceinline__ Fetched fetch(const RenderRecord* __restrict__ rec, u
 constexpr int kOrderBuckets = 33;
 constexpr uint32_t kLongList = 1024;
 
-__global__ void __launch_bounds__(1024) tile_order_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
-                                                          uint32_t n_pairs, uint32_t* __restrict__ order) {
+__device__ __forceinline__ int order_bucket(const uint32_t* __restrict__ ranges, int t, uint32_t n_pairs) {
+  const uint32_t e = min(ranges[2 * t + 1], n_pairs), s = min(ranges[2 * t], e);
+  const uint32_t len = e - s;
+  return len == 0 ? kOrderBuckets - 1 : (kOrderBuckets - 2) - (31 - __clz(len));
+}
+
+// Lanes of the wave whose bucket equals this lane's (6 ballots over its bits).
+__device__ __forceinline__ uint64_t same_bucket(int b, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const bool bit = (b >> k) & 1;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+// Counting sort of the tiles by bucket in two launches over blocks of 256
+// tiles: per-block bucket counts, then each block finds its buckets' bases
+// (all blocks' counts are a few hundred words) and scatters its tiles. Each
+// wave groups its tiles by bucket with ballots, so LDS atomics are per bucket
+// per wave rather than per tile.
+constexpr int kOrderBlock = 256;
+
+__global__ void __launch_bounds__(kOrderBlock) order_count_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                                  uint32_t n_pairs, uint32_t* __restrict__ counts) {
   __shared__ uint32_t cnt[kOrderBuckets];
-  __shared__ uint32_t off[kOrderBuckets];
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0u;
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    const uint32_t e = min(ranges[2 * t + 1], n_pairs), s = min(ranges[2 * t], e);
-    const uint32_t len = e - s;
-    const int b = len == 0 ? kOrderBuckets - 1 : (kOrderBuckets - 2) - (31 - __clz(len));
-    atomicAdd(&cnt[b], 1u);
+  const int t = blockIdx.x * kOrderBlock + threadIdx.x;
+  const bool valid = t < n_tiles;
+  const int b = valid ? order_bucket(ranges, t, n_pairs) : 0;
+  const uint64_t m = same_bucket(b, valid);
+  if (valid && (m & lt) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(m));
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets) counts[threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                                    uint32_t n_pairs,
+                                                                    const uint32_t* __restrict__ counts,
+                                                                    uint32_t* __restrict__ order) {
+  __shared__ uint32_t base[kOrderBuckets];
+  __shared__ uint32_t wave_cnt[kOrderBlock / 64][kOrderBuckets];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int nb = gridDim.x;
+  if (threadIdx.x < kOrderBuckets) {
+    uint32_t total = 0, before = 0;
+    for (int k = 0; k < nb; ++k) {
+      const uint32_t c = counts[threadIdx.x * nb + k];
+      total += c;
+      before += k < (int)blockIdx.x ? c : 0u;
+    }
+    base[threadIdx.x] = before;
+    wave_cnt[0][threadIdx.x] = total;  // bucket totals, scanned below
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    for (int b = 0; b < kOrderBuckets; ++b) {
-      off[b] = run;
-      run += cnt[b];
+    for (int k = 0; k < kOrderBuckets; ++k) {
+      base[k] += run;
+      run += wave_cnt[0][k];
     }
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    const uint32_t e = min(ranges[2 * t + 1], n_pairs), s = min(ranges[2 * t], e);
-    const uint32_t len = e - s;
-    const int b = len == 0 ? kOrderBuckets - 1 : (kOrderBuckets - 2) - (31 - __clz(len));
-    order[atomicAdd(&off[b], 1u)] = (uint32_t)t;
+  for (int i = threadIdx.x; i < (kOrderBlock / 64) * kOrderBuckets; i += kOrderBlock) (&wave_cnt[0][0])[i] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * kOrderBlock + threadIdx.x;
+  const bool valid = t < n_tiles;
+  const int b = valid ? order_bucket(ranges, t, n_pairs) : 0;
+  const uint64_t m = same_bucket(b, valid);
+  if (valid && (m & lt) == 0) wave_cnt[wid][b] = (uint32_t)__popcll(m);
+  __syncthreads();
+  if (valid) {
+    uint32_t pos = base[b] + (uint32_t)__popcll(m & lt);
+    for (int w = 0; w < wid; ++w) pos += wave_cnt[w][b];
+    if (pos < (uint32_t)n_tiles) order[pos] = (uint32_t)t;
   }
 }
 
@@ -542,9 +597,15 @@ __global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __rest
 
 }  // namespace
 
-hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order,
+int64_t tile_order_scratch(int n_tiles) { return (int64_t)kOrderBuckets * ((n_tiles + kOrderBlock - 1) / kOrderBlock); }
+
+// counts: tile_order_scratch(n_tiles) words
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order, uint32_t* counts,
                              hipStream_t stream) {
-  tile_order_kernel<<<1, 1024, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, order);
+  if (n_tiles <= 0) return hipSuccess;
+  const int nb = (n_tiles + kOrderBlock - 1) / kOrderBlock;
+  order_count_kernel<<<nb, kOrderBlock, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, counts);
+  order_scatter_kernel<<<nb, kOrderBlock, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, counts, order);
   return hipGetLastError();
 }
 

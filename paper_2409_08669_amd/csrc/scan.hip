@@ -1,5 +1,6 @@
 // InclusiveSum (Sec. 3.2, stage 2): offsets of each Gaussian's pairs, taken
-// over the Gaussians in depth order (out[r] = sum of in[idx[r']] for r' <= r).
+// over the Gaussians in depth order (out[r] = sum of in[r'] for r' <= r; the
+// depth sort's last pass writes tiles_touched in that order).
 // Reduce-then-scan in two launches: per-block totals, then each block adds up
 // the totals of the blocks before it (a few hundred words, read from L2) and
 // rescans its 2048 entries from that prefix.
@@ -36,22 +37,20 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* smem4,
   return s + before;
 }
 
-__global__ void __launch_bounds__(kScanThreads) block_totals_kernel(const uint32_t* __restrict__ in,
-                                                                    const uint32_t* __restrict__ idx, int64_t n,
+__global__ void __launch_bounds__(kScanThreads) block_totals_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                     uint32_t* __restrict__ partials) {
   __shared__ uint32_t smem[4];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
   uint32_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) s += in[idx[base + i]];
+    if (base + i < n) s += in[base + i];
   uint32_t total;
   (void)block_incl_scan(s, smem, &total);
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_t* __restrict__ in,
-                                                                   const uint32_t* __restrict__ idx, int64_t n,
+__global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                    const uint32_t* __restrict__ partials,
                                                                    uint32_t* __restrict__ out) {
   __shared__ uint32_t smem[4];
@@ -60,7 +59,7 @@ __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_
   uint32_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = base + i < n ? in[idx[base + i]] : 0u;
+    v[i] = base + i < n ? in[base + i] : 0u;
     s += v[i];
   }
   // prefix of the earlier blocks' totals
@@ -81,12 +80,12 @@ __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_
 
 int64_t inclusive_sum_partials(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
 
-hipError_t launch_inclusive_sum(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n,
-                                uint32_t* partials, hipStream_t stream) {
+hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
+                                hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = inclusive_sum_partials(n);
-  block_totals_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, idx, n, partials);
-  scan_blocks_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, idx, n, partials, out);
+  block_totals_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials);
+  scan_blocks_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials, out);
   return hipGetLastError();
 }
 

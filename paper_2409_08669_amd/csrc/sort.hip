@@ -110,7 +110,9 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                              int64_t n, int shift, KeyMap km,
                                                              const uint32_t* __restrict__ offsets, int64_t nb,
-                                                             const uint32_t* __restrict__ totals) {
+                                                             const uint32_t* __restrict__ totals,
+                                                             const uint32_t* __restrict__ gather_src,
+                                                             uint32_t* __restrict__ gather_dst) {
   __shared__ uint32_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
   __shared__ uint32_t wcnt[4][kRadix];
@@ -188,8 +190,10 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
     const uint32_t dd = digit_of(key, km, shift);
     const uint32_t o = glob_base[dd] + (uint32_t)i - blk_start[dd];
     if (o < (uint64_t)n) {  // always true for a correct ranking; keeps a fault impossible
+      const uint32_t val = svals[i];
       kout[o] = key;
-      vout[o] = svals[i];
+      vout[o] = val;
+      if (gather_dst) gather_dst[o] = gather_src[val];  // the caller's per-value array, in sorted order
     }
   }
 }
@@ -202,10 +206,12 @@ int64_t sort_scratch_entries(int64_t n) {
 }
 
 // Stable sort of (key, value) by min(key - bias, lim), whose n_bits low bits
-// are all that vary. totals: 256 words of scratch.
+// are all that vary. totals: 256 words of scratch. If gather_dst is given,
+// the last pass also writes gather_dst[i] = gather_src[value i] (values must
+// index gather_src).
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
                              uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
-                             hipStream_t stream) {
+                             hipStream_t stream, const uint32_t* gather_src, uint32_t* gather_dst) {
   *result_buffer = 0;
   if (n <= 1 || n_bits <= 0) return hipSuccess;
   const int n_pass = (n_bits + 7) / 8;
@@ -218,8 +224,10 @@ hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, in
   for (int p = 0; p < n_pass; ++p) {
     upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
     digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
-    downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
-                                                                    vals[cur ^ 1], n, 8 * p, km, counts, nb, totals);
+    const bool last = p == n_pass - 1;
+    downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(
+        keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals,
+        last ? gather_src : nullptr, last ? gather_dst : nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
