@@ -14,8 +14,8 @@
 // of a scene usually need three 8-bit passes instead of four.
 //
 // Each pass is reduce-then-scan: per-workgroup digit counts, one workgroup
-// per digit scans them into scatter offsets, and a downsweep ranks 4096 keys
-// per workgroup in LDS and scatters them. Ranking is stable and uses wave64
+// per digit scans them into scatter offsets, and a downsweep ranks the
+// workgroup's 2048 or 4096 keys in LDS and scatters them. Ranking is stable and uses wave64
 // ballots: the lanes of a row that share a digit are found with eight
 // ballots, one per digit bit, and counted with popcounts, so no atomics decide
 // an order. (A single-launch decoupled look-back was tried first; its chain of
@@ -27,8 +27,12 @@ namespace adr {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kTileKeys = kThreads * kItems;  // 4096 keys per workgroup
+// Keys per lane: 8 (2048 per workgroup) up to 1.5M keys, so that a million
+// depth keys still give every CU a few workgroups; 16 (4096) above that.
+constexpr int kSmallSortItems = 8, kLargeSortItems = 16;
+constexpr int64_t kSmallSortMax = 1536 * 1024;
+
+__host__ __device__ constexpr int sort_items(int64_t n) { return n <= kSmallSortMax ? kSmallSortItems : kLargeSortItems; }
 constexpr int kRadix = 256;
 constexpr int kMaxPasses = 4;
 
@@ -63,12 +67,14 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, KeyMap km, int shift) {
 }
 
 // Per-workgroup digit counts of one pass: counts[d * nb + b].
+template <int kItems>
 __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __restrict__ kin, int64_t n, int shift,
                                                            KeyMap km, uint32_t* __restrict__ counts, int64_t nb) {
   __shared__ uint32_t wh[4][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int i = tid; i < 4 * kRadix; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
+  constexpr int kTileKeys = kThreads * kItems;
   const int64_t wave_base = (int64_t)blockIdx.x * kTileKeys + (int64_t)wid * (kItems * 64);
 #pragma unroll 4
   for (int r = 0; r < kItems; ++r) {
@@ -105,6 +111,7 @@ __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __res
 
 // Stable rank of the workgroup's 4096 keys and scatter to the offsets of the
 // pass.
+template <int kItems>
 __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -113,6 +120,7 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
                                                              const uint32_t* __restrict__ totals,
                                                              const uint32_t* __restrict__ gather_src,
                                                              uint32_t* __restrict__ gather_dst) {
+  constexpr int kTileKeys = kThreads * kItems;
   __shared__ uint32_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
   __shared__ uint32_t wcnt[4][kRadix];
@@ -201,7 +209,8 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
 }  // namespace
 
 int64_t sort_scratch_entries(int64_t n) {
-  const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
+  const int64_t tile = (int64_t)kThreads * sort_items(n);
+  const int64_t nb = (n + tile - 1) / tile;
   return (int64_t)kRadix * (nb > 0 ? nb : 1);  // digit counts / offsets [256][nb]
 }
 
@@ -216,18 +225,28 @@ hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, in
   if (n <= 1 || n_bits <= 0) return hipSuccess;
   const int n_pass = (n_bits + 7) / 8;
   if (n_pass > kMaxPasses) return hipErrorInvalidValue;
-  const int64_t nb = (n + kTileKeys - 1) / kTileKeys;
+  const int items = sort_items(n);
+  const int64_t tile = (int64_t)kThreads * items;
+  const int64_t nb = (n + tile - 1) / tile;
   uint32_t* counts = scratch;
   const KeyMap km{bias, lim};
   hipError_t e;
   int cur = 0;
   for (int p = 0; p < n_pass; ++p) {
-    upsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
-    digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
     const bool last = p == n_pass - 1;
-    downsweep_kernel<<<dim3((unsigned)nb), kThreads, 0, stream>>>(
-        keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals,
-        last ? gather_src : nullptr, last ? gather_dst : nullptr);
+    const uint32_t* gs = last ? gather_src : nullptr;
+    uint32_t* gd = last ? gather_dst : nullptr;
+    if (items == kSmallSortItems) {
+      upsweep_kernel<kSmallSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
+      digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
+      downsweep_kernel<kSmallSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd);
+    } else {
+      upsweep_kernel<kLargeSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
+      digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
+      downsweep_kernel<kLargeSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
