@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="measured length of the serving run (0 = skip; serving is switched off in this "
+                         "build); 2 s of warm-up come first")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--cpu-tiles", type=int, default=2048)
     ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only"], default=None,
                     help="time one mode only (for profiler runs)")
@@ -269,6 +274,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, cam, args.cpu_tiles, n_tiles)
+    serving = None
+    if args.serve_seconds > 0:
+        del sg, ws, out, images
+        torch.cuda.empty_cache()
+        serving = serve_benchmark(P, args)
 
     line = {
         "metric": METRIC,
@@ -300,10 +310,106 @@ def main():
         "load_imbalance_E_exec_over_E_alg": results["aabb"].get("load_imbalance_E_exec_over_E_alg"),
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "serving_p99_ms": None,
+        "serving_p99_ms": serving["p99_ms"] if serving else None,
+        "serving": serving,
         "paper_context": "paper reports ~3.1x over 3DGS (Ours-Full, RTX 3090, trained scenes); AABB alone 1.65-2.11x",
     }
     print(json.dumps(line), flush=True)
+
+
+def serve_benchmark(P, args):
+    """Serving load: resident scenes of 0.5, 1, 2 and 3M Gaussians (the
+    headline generator, seeds 1..4), Poisson arrivals at args.serve_rate
+    requests/s, each request a uniformly drawn scene and resolution (640x480,
+    1280x720, 1920x1080, 3840x2160) and an orbit pose (azimuth U[0, 360),
+    elevation U[5, 45] degrees, radius 30), AABB culling. Latency = arrival
+    (the scheduled time, on the server's clock) to the frame's completion on
+    the device; 2 s of warm-up arrivals are not counted."""
+    import threading
+    import numpy as np
+    import torch
+    from synth import scene_clusters, camera_orbit
+
+    sizes = (500_000, 1_000_000, 2_000_000, 3_000_000)
+    res = ((640, 480), (1280, 720), (1920, 1080), (3840, 2160))
+    log(f"serving: generating {len(sizes)} resident scenes")
+    scenes = [P.Scene.from_synth(scene_clusters(n, seed=1 + i)) for i, n in enumerate(sizes)]
+    rng = np.random.default_rng(2024)
+    warm, total = 2.0, 2.0 + args.serve_seconds
+    t, arrivals = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / args.serve_rate)
+        if t >= total:
+            break
+        w, h = res[rng.integers(0, len(res))]
+        cam = camera_orbit(30.0, rng.uniform(5.0, 45.0), rng.uniform(0.0, 360.0), int(w), int(h))
+        arrivals.append((t, int(rng.integers(0, len(scenes))), cam))
+    # output buffers: a pool sized for the largest frame, recycled once a
+    # request completes (waiting for a free one counts toward latency)
+    n_buf = 32
+    wmax, hmax = res[-1]
+    pool = [dict(image=torch.empty((3, hmax, wmax), device="cuda")) for _ in range(n_buf)]
+    free = list(range(n_buf))
+    cv = threading.Condition()
+    server = P.Server(args.serve_slots)
+    params = P.RenderParams(cull=P.ADR_CULL_AABB)
+    pending, done = [], []
+
+    def collect():
+        while True:
+            with cv:
+                while not pending:
+                    cv.wait()
+                item = pending.pop(0)
+            if item is None:
+                return
+            arrival, ticket, b, sc, cam = item
+            info = server.wait(ticket)
+            with cv:
+                free.append(b)
+                done.append((arrival, info, sc, cam.width * cam.height))
+                cv.notify_all()
+
+    th = threading.Thread(target=collect)
+    th.start()
+    log(f"serving: {len(arrivals)} requests over {total:.0f} s at {args.serve_rate:.0f}/s on {args.serve_slots} slots")
+    t0 = P.clock_s() + 0.2
+    for t_arr, sc, cam in arrivals:
+        arrival = t0 + t_arr
+        while P.clock_s() < arrival:
+            time.sleep(max(0.0, min(arrival - P.clock_s() - 2e-4, 1e-3)))
+        with cv:
+            while not free:
+                cv.wait()
+            b = free.pop()
+        img = pool[b]["image"]
+        view = img.view(-1)[: 3 * cam.height * cam.width].view(3, cam.height, cam.width)
+        ticket = server.submit(scenes[sc], cam, params, view)
+        with cv:
+            pending.append((arrival, ticket, b, sc, cam))
+            cv.notify_all()
+    with cv:
+        pending.append(None)
+        cv.notify_all()
+    th.join()
+    server.close()
+    lat = np.array([(info["done_s"] - arr) * 1e3 for arr, info, _, _ in done if arr - t0 >= warm])
+    span = max(info["done_s"] for _, info, _, _ in done) - (t0 + warm)
+    by_res = {}
+    for arr, info, sc, px in done:
+        if arr - t0 >= warm:
+            by_res.setdefault(px, []).append((info["done_s"] - arr) * 1e3)
+    names = {w * h: f"{w}x{h}" for w, h in res}
+    return {"rate_per_s": args.serve_rate, "seconds": args.serve_seconds, "slots": args.serve_slots,
+            "requests": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3),
+            "frames_per_s": round(lat.size / span, 1),
+            "p50_ms_by_resolution": {names[k]: round(float(np.percentile(v, 50)), 3) for k, v in sorted(by_res.items())},
+            "p99_ms_by_resolution": {names[k]: round(float(np.percentile(v, 99)), 3) for k, v in sorted(by_res.items())},
+            "scenes": list(sizes), "cull": "aabb",
+            "workload": "Poisson arrivals; scene uniform over the resident scenes; resolution uniform over "
+                        "640x480, 1280x720, 1920x1080, 3840x2160; orbit pose radius 30, elevation U[5,45], "
+                        "azimuth U[0,360)"}
 
 
 def cpu_baseline(scene, cam, n_tiles_sample, n_tiles):

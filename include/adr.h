@@ -12,8 +12,9 @@
  * Conventions shared by every entry point:
  *  - All device pointers refer to memory of the current HIP device.
  *  - Work is enqueued on the caller's stream (a hipStream_t passed as void*;
- *    NULL = the null stream). adr_render waits once per frame for a 16-byte
- *    device-to-host copy (the pair count); everything else is asynchronous.
+ *    NULL = the null stream). adr_render waits once per frame, after
+ *    Preprocess, for the pair count (the GPU writes it to mapped pinned host
+ *    memory); everything else is asynchronous.
  *  - Functions return ADR_OK or a negative adr_status; adr_last_error()
  *    returns a thread-local message for the last failure. No C++ exception
  *    crosses this boundary.
@@ -185,6 +186,46 @@ int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
  * [4] key bits the depth sort of the Gaussians covered (the visible depth
  * keys' range; 8 per radix pass). Returns the number of entries written. */
 int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n);
+
+/* Serving: resident scenes, concurrent requests.
+ *
+ * A server owns n_slots render slots, each a host thread with its own HIP
+ * stream (default priority) and workspace on the device current at
+ * adr_server_create. Requests start in submission order as slots free up, so
+ * up to n_slots frames are in flight on the device at once (their kernels
+ * overlap); each request's outputs are bitwise those adr_render gives for it
+ * alone. Admission: a request waits in the queue while every slot is busy,
+ * and a slot's workspace grows to the largest frame it has rendered, so
+ * device memory is bounded by n_slots such workspaces plus the resident
+ * scenes. The scene, camera, params and frame of a request are copied at
+ * submission; the frame's output buffers (caller-owned device memory) and the
+ * scene must stay valid until adr_server_wait returns for its ticket. */
+typedef struct adr_server adr_server;
+
+typedef struct {
+  int32_t status;  /* adr_status of the render (ADR_OK, or its error; see adr_last_error after the wait) */
+  int64_t n_pairs; /* the frame's Gaussian-tile pair count */
+  double submit_s; /* adr_clock_s() when submitted, when a slot started it, when its stream finished */
+  double start_s;
+  double done_s;
+} adr_request_info;
+
+/* n_slots in 1..64. Returns ADR_E_INVALID otherwise, ADR_E_HIP or ADR_E_OOM
+ * when a stream or workspace cannot be created. This build returns
+ * ADR_E_UNSUPPORTED for valid arguments: serving is switched off until the
+ * cause of a GPU fault seen in its first test is found. */
+adr_status adr_server_create(int32_t n_slots, adr_server** out);
+/* Finishes every queued and running request, then releases the slots. */
+void adr_server_destroy(adr_server* server);
+/* Queues one frame; writes its ticket. Argument errors are reported here,
+ * before anything is queued. */
+adr_status adr_server_submit(adr_server* server, const adr_scene* scene, const adr_camera* cam,
+                             const adr_render_params* params, const adr_frame* frame, uint64_t* ticket);
+/* Blocks until the ticket's frame has finished on the device, fills info and
+ * retires the ticket. ADR_E_INVALID for an unknown ticket. */
+adr_status adr_server_wait(adr_server* server, uint64_t ticket, adr_request_info* info);
+/* Seconds of the steady clock the server time-stamps requests with. */
+double adr_clock_s(void);
 
 const char* adr_last_error(void);
 const char* adr_version(void);

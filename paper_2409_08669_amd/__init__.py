@@ -14,7 +14,9 @@ from .binding import (  # noqa: F401
     AdrError,
     RenderParams,
     Scene,
+    Server,
     Workspace,
+    clock_s,
     load,
     render,
     render_frame,

@@ -37,6 +37,7 @@ EXPORTS = (
     "adr_create_scene", "adr_destroy_scene", "adr_scene_size", "adr_scene_bytes",
     "adr_workspace_create", "adr_workspace_destroy", "adr_render", "adr_render_backward",
     "adr_workspace_stage_times", "adr_workspace_counters", "adr_last_error", "adr_version",
+    "adr_server_create", "adr_server_destroy", "adr_server_submit", "adr_server_wait", "adr_clock_s",
 )
 
 
@@ -107,12 +108,28 @@ def load(path=None):
     lib.adr_workspace_stage_times.restype = i32
     lib.adr_workspace_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
     lib.adr_workspace_counters.restype = i32
+    lib.adr_server_create.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.adr_server_create.restype = i32
+    lib.adr_server_destroy.argtypes = [vp]
+    lib.adr_server_destroy.restype = None
+    lib.adr_server_submit.argtypes = [vp, vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
+                                      ctypes.POINTER(adr_frame), ctypes.POINTER(ctypes.c_uint64)]
+    lib.adr_server_submit.restype = i32
+    lib.adr_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(adr_request_info)]
+    lib.adr_server_wait.restype = i32
+    lib.adr_clock_s.argtypes = []
+    lib.adr_clock_s.restype = ctypes.c_double
     lib.adr_last_error.argtypes = []
     lib.adr_last_error.restype = ctypes.c_char_p
     lib.adr_version.argtypes = []
     lib.adr_version.restype = ctypes.c_char_p
     _lib = lib
     return lib
+
+
+class adr_request_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
 
 
 def last_error() -> str:
@@ -325,3 +342,57 @@ def load_stats_from_sums(sums, n_pixels: int):
     mean = s1 / n_pixels
     var = (n_pixels * s2 - s1 * s1) / (n_pixels * n_pixels)
     return mean, math.sqrt(max(var, 0.0))
+
+
+def clock_s() -> float:
+    """The steady clock the server time-stamps requests with (seconds)."""
+    return float(load().adr_clock_s())
+
+
+class Server:
+    """adr_server: n_slots render slots (host thread + HIP stream + workspace
+    each) consuming queued frame requests over resident scenes."""
+
+    def __init__(self, n_slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(load().adr_server_create(int(n_slots), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}  # ticket -> objects that must outlive the request
+
+    def submit(self, scene: Scene, cam, params: RenderParams, image, final_t=None, l_iter=None, l_blend=None,
+               load_sums=None) -> int:
+        """Queues one frame into caller-allocated device tensors; returns its
+        ticket. The tensors and the scene must stay alive until wait()."""
+        f = adr_frame()
+        f.image, f.final_t, f.l_iter, f.l_blend = _ptr(image), _ptr(final_t), _ptr(l_iter), _ptr(l_blend)
+        f.load_sums = _ptr(load_sums)
+        c, p = camera_to_c(cam), params.to_c()
+        t = ctypes.c_uint64()
+        _check(load().adr_server_submit(self._h, scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
+                                        ctypes.byref(t)))
+        self._keep[int(t.value)] = (scene, image, final_t, l_iter, l_blend, load_sums)
+        return int(t.value)
+
+    def wait(self, ticket: int) -> dict:
+        """Blocks until the frame is done; returns its status, pair count and
+        time stamps (submit, start, done; seconds of clock_s())."""
+        info = adr_request_info()
+        _check(load().adr_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(info)))
+        self._keep.pop(int(ticket), None)
+        out = dict(status=int(info.status), n_pairs=int(info.n_pairs), submit_s=info.submit_s,
+                   start_s=info.start_s, done_s=info.done_s)
+        if info.status != ADR_OK:
+            raise AdrError(int(info.status), last_error())
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().adr_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

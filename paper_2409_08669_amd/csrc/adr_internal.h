@@ -165,6 +165,9 @@ constexpr int kHistWords = 4 * 256;  // digit histograms of up to four 8-bit pas
 
 // Thread-local error message for adr_last_error.
 void set_error(const std::string& msg);
+// Host-side checks of adr_render's arguments (everything but the workspace).
+adr_status validate_render_args(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                const adr_frame* out);
 adr_status hip_fail(hipError_t e, const char* what);
 
 #define ADR_HIP(call)                                          \

@@ -164,9 +164,10 @@ extern "C" void adr_workspace_destroy(adr_workspace* ws) {
   delete ws;
 }
 
-static adr_status validate(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
-                           const adr_frame* out, const adr_workspace* ws) {
-  if (!scene || !cam || !p || !out || !ws) {
+namespace adr {
+adr_status validate_render_args(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                const adr_frame* out) {
+  if (!scene || !cam || !p || !out) {
     set_error("adr_render: NULL argument");
     return ADR_E_INVALID;
   }
@@ -204,6 +205,16 @@ static adr_status validate(const adr_scene* scene, const adr_camera* cam, const 
     return ADR_E_INVALID;
   }
   return ADR_OK;
+}
+}  // namespace adr
+
+static adr_status validate(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                           const adr_frame* out, const adr_workspace* ws) {
+  if (!ws) {
+    set_error("adr_render: NULL argument");
+    return ADR_E_INVALID;
+  }
+  return validate_render_args(scene, cam, p, out);
 }
 
 extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,

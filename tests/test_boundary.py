@@ -126,3 +126,30 @@ def test_package_does_not_import_the_oracle():
         text = f.read_text()
         assert "import oracle" not in text and "from oracle" not in text, f
         assert "adr_oracle" not in text, f
+
+
+def test_server_rejects_bad_arguments_on_host():
+    """Serving entry points validate on the host before touching a device."""
+    binding, lib = _lib()
+    h = ctypes.c_void_p()
+    for n in (0, -1, 65):
+        assert lib.adr_server_create(n, ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert lib.adr_server_create(4, None) == binding.ADR_E_INVALID
+    t = ctypes.c_uint64()
+    cam = binding.adr_camera()
+    p = binding.RenderParams().to_c()
+    f = binding.adr_frame()
+    assert lib.adr_server_submit(None, None, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f),
+                                 ctypes.byref(t)) == binding.ADR_E_INVALID
+    fake = ctypes.c_void_p(1)  # never dereferenced: validation fails first
+    assert lib.adr_server_submit(fake, fake, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f),
+                                 ctypes.byref(t)) == binding.ADR_E_INVALID  # no image, zero-size camera
+    assert lib.adr_server_wait(None, 1, None) == binding.ADR_E_INVALID
+    assert lib.adr_clock_s() > 0.0
+
+
+def test_serving_is_switched_off_and_says_so():
+    binding, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.adr_server_create(4, ctypes.byref(h)) == binding.ADR_E_UNSUPPORTED
+    assert "switched off" in binding.last_error() and not h.value
