@@ -360,6 +360,9 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
   __shared__ Staged stage[4][65];
   __shared__ float4 stage_col[4][65];
   __shared__ uint32_t stage_gid[4][65];
+  // per wave, per step i of the candidate pass: byte t = the slot of sub-block
+  // t's i-th entry (64 past the end of its list); word 64 is all 64
+  __shared__ uint32_t step_table[4][65];
   const int tile = (int)min(order[blockIdx.x], (uint32_t)(n_tiles - 1));
   const int W = cam.width, H = cam.height;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -379,6 +382,7 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
   Staged* my = stage[wid];
   float4* my_col = stage_col[wid];
   uint32_t* my_gid = stage_gid[wid];
+  uint32_t* my_steps = step_table[wid];
   if (lane == 0) {  // exponent -1e30: alpha 0, colour 0; evaluating it changes nothing
     Staged z;
     z.a = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -386,6 +390,7 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
     my[64] = z;
     my_col[64] = make_float4(0.f, 0.f, 0.f, 0.f);
     my_gid[64] = 0u;
+    my_steps[64] = 0x40404040u;
   }
 
   // ranges come from this frame's sorted keys; the clamps only make a
@@ -428,7 +433,13 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
   }
   for (uint32_t base = s; base < e; base += 64) {
     const uint64_t any = hm.m[0] | hm.m[1] | hm.m[2] | hm.m[3];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    my_steps[lane] = 0x40404040u;  // every entry past a list's end names the null slot
     if ((any >> lane) & 1ull) {
+      uint8_t* steps_bytes = reinterpret_cast<uint8_t*>(my_steps);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if ((hm.m[t] >> lane) & 1ull) steps_bytes[4 * __popcll(hm.m[t] & lt) + t] = (uint8_t)lane;
       Staged st;
       st.a = make_float4((float)(f_b.x - (double)qx0), (float)(f_b.y - (double)qy0), f_b.q.x, f_b.q.y);
       const float band = bl.exact ? f_b.dq + bl.band_floor : 0.f;
@@ -439,7 +450,6 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
     // colours are needed only by phase 2: their load overlaps phase 1
     const float4 col_b = *reinterpret_cast<const float4*>(&rec[((any >> lane) & 1ull) ? g_b : 0u].r);
     // the sub-block's entries of this batch, in list order: the set bits
-    uint64_t my_mask = sb == 0 ? hm.m[0] : sb == 1 ? hm.m[1] : sb == 2 ? hm.m[2] : hm.m[3];
     const int n_iter = max(max(__popcll(hm.m[0]), __popcll(hm.m[1])), max(__popcll(hm.m[2]), __popcll(hm.m[3])));
     // issue the next batches' loads before evaluating this one
     hm = sub_masks(base + 64 + lane < e ? box_n1 : kNoBox, qx0, qy0);
@@ -463,7 +473,13 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
     // unchanged. (Steps past a list's end read the null slot.)
     uint64_t cand = 0;
     {
-      int s0 = next_slot(my_mask), s1 = next_slot(my_mask);
+      // Step i reads one word of the batch's step table (the same address
+      // for every lane, read two steps ahead) and takes its sub-block's byte:
+      // the slot of the sub-block's i-th entry, or 64 past its list's end.
+      const uint32_t shift = 8u * (uint32_t)sb;
+      auto slot_at = [&](uint32_t word) -> int { return (int)__builtin_amdgcn_ubfe(word, shift, 8u); };
+      uint32_t w2 = my_steps[2];
+      int s0 = slot_at(my_steps[0]), s1 = slot_at(my_steps[1]);
       float4 A0 = my[s0].a, B0 = my[s0].b, A1, B1;
       ready(A0);
       ready(B0);
@@ -471,19 +487,21 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
       for (int i = 0; i < n_iter; i += 2) {
         A1 = my[s1].a;
         B1 = my[s1].b;
+        const uint32_t w3 = my_steps[min(i + 3, 64)];
         __builtin_amdgcn_sched_barrier(0);  // issue the reads here, one step before their use
         float q = quad_form(A0, B0, fx, fy);
-        cand |= (q >= fmaf(-2.f, B0.w, bl.q_low) && s0 < 64) ? (1ull << (s0 & 63)) : 0ull;
-        s0 = next_slot(my_mask);
+        cand |= (q >= fmaf(-2.f, B0.w, bl.q_low)) ? (1ull << (s0 & 63)) : 0ull;  // never true for slot 64
+        s0 = slot_at(w2);
         __builtin_amdgcn_sched_barrier(0);  // the step above completes before the wait below
         ready(A1);
         ready(B1);
         A0 = my[s0].a;
         B0 = my[s0].b;
+        w2 = my_steps[min(i + 4, 64)];
         __builtin_amdgcn_sched_barrier(0);
         q = quad_form(A1, B1, fx, fy);
-        cand |= (q >= fmaf(-2.f, B1.w, bl.q_low) && s1 < 64) ? (1ull << (s1 & 63)) : 0ull;
-        s1 = next_slot(my_mask);
+        cand |= (q >= fmaf(-2.f, B1.w, bl.q_low)) ? (1ull << (s1 & 63)) : 0ull;
+        s1 = slot_at(w3);
         __builtin_amdgcn_sched_barrier(0);
         ready(A0);
         ready(B0);
