@@ -84,7 +84,9 @@ struct BlendArgs {
   float t_min;
   float q_low;              // log2(alpha_low) rounded to float
   float band_floor;         // added to each Gaussian's exponent error bound (0: no FP64 bands)
-  float t_band;             // 1: FP64 transmittance replays near t_min, 0: none
+  // FP64 transmittance replay when |T - t_min| < t_err_scale D + t_err_floor,
+  // D the running bound on |T - T_fp64|; both 0: no replays
+  float t_err_scale, t_err_floor;
   double alpha_low_d, alpha_max_d, t_min_d;
   float bg[3];
   int32_t lb_cap;

@@ -261,7 +261,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   // transmittance band follows a running error bound per pixel.
   bl.exact = (p->flags & ADR_FLAG_NO_EXACT_BAND) ? 0 : 1;
   bl.band_floor = bl.exact ? 0x1p-19f : 0.f;
-  bl.t_band = bl.exact ? 1.f : 0.f;
+  bl.t_err_scale = bl.exact ? 1.5f : 0.f;  // margin over first-order terms left out of D
+  bl.t_err_floor = bl.exact ? bl.t_min * 0x1p-21f : 0.f;  // t_min's rounding to float and the subtraction's
   bl.alpha_low_d = p->alpha_low;
   bl.alpha_max_d = p->alpha_max;
   bl.t_min_d = p->t_min;

@@ -69,12 +69,29 @@ __device__ __forceinline__ double alpha_fp64(const ExactRecord& e, double x, dou
   return fmin(alpha_max, e.opacity * exp(power));
 }
 
+// The out-of-line FP64 helpers below receive generic pointers; reading
+// through global-address-space pointers lets their loads be waited for one by
+// one (a generic load also counts as an LDS access, so every wait for one
+// would wait for all).
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
 // FP64 alpha of Gaussian g at pixel (pi, pj); kept out of line so the rare
 // FP64 path does not raise the register count of the blend loop.
-__device__ __noinline__ double alpha_fp64_at(const RenderRecord* __restrict__ rec,
-                                             const ExactRecord* __restrict__ exact, uint32_t g, int pi, int pj,
+__device__ __noinline__ double alpha_fp64_at(const RenderRecord* __restrict__ rec_,
+                                             const ExactRecord* __restrict__ exact_, uint32_t g, int pi, int pj,
                                              double alpha_max) {
-  return alpha_fp64(exact[g], rec[g].x, rec[g].y, pi, pj, alpha_max);
+  const auto* rec = global_ptr(rec_);
+  const auto* exact = global_ptr(exact_);
+  ExactRecord e;
+  e.ca = exact[g].ca;
+  e.cb = exact[g].cb;
+  e.cc = exact[g].cc;
+  e.opacity = exact[g].opacity;
+  const double x = rec[g].x, y = rec[g].y;
+  return alpha_fp64(e, x, y, pi, pj, alpha_max);
 }
 
 // log2-domain exponent of a staged Gaussian at the lane's pixel (lx, ly),
@@ -89,27 +106,38 @@ __device__ __forceinline__ float quad_form(const float4& A, const float4& B, flo
 // FP64 transmittance of pixel (ri, rj) after list entries [s, k_now]: the
 // wave's lanes take every 64th entry and the partial products are combined.
 // A lane's id loads run two entries ahead and its box loads one entry ahead
-// (clamped to the range, so none waits on a branch); its product runs over
-// its entries in list order.
-__device__ __noinline__ double replay_fp64(const RenderRecord* __restrict__ rec,
-                                           const ExactRecord* __restrict__ exact,
-                                           const uint32_t* __restrict__ vals, uint32_t n_gauss, uint32_t s,
+// (clamped to the range, so none waits on a branch); the FP64 record of an
+// entry whose box holds the pixel is read with a single wait. A lane's
+// product runs over its entries in list order.
+__device__ __noinline__ double replay_fp64(const RenderRecord* __restrict__ rec_,
+                                           const ExactRecord* __restrict__ exact_,
+                                           const uint32_t* __restrict__ vals_, uint32_t n_gauss, uint32_t s,
                                            uint32_t k_now, int ri, int rj, int lane, const BlendArgs& bl) {
+  const auto* rec = global_ptr(rec_);
+  const auto* exact = global_ptr(exact_);
+  const auto* vals = global_ptr(vals_);
+  const double alpha_max = bl.alpha_max_d, alpha_low = bl.alpha_low_d;
   double prod = 1.0;
   uint64_t kk = (uint64_t)s + lane;
   const uint64_t kl = k_now;
   uint32_t g = min(vals[min(kk, kl)], n_gauss - 1);
   uint32_t g_n = min(vals[min(kk + 64, kl)], n_gauss - 1);
-  uint2 bx = *reinterpret_cast<const uint2*>(&rec[g].box_x);
+  uint32_t bx = rec[g].box_x, by = rec[g].box_y;
   for (; kk <= kl; kk += 64) {
-    const uint2 bx_n = *reinterpret_cast<const uint2*>(&rec[g_n].box_x);
+    const uint32_t bx_n = rec[g_n].box_x, by_n = rec[g_n].box_y;
     const uint32_t raw_nn = vals[min(kk + 128, kl)];
-    if (box_has(bx.x, bx.y, ri, rj)) {
-      const double ad = alpha_fp64(exact[g], rec[g].x, rec[g].y, ri, rj, bl.alpha_max_d);
-      if (ad >= bl.alpha_low_d) prod *= 1.0 - ad;
+    if (box_has(bx, by, ri, rj)) {
+      ExactRecord e;
+      e.ca = exact[g].ca;
+      e.cb = exact[g].cb;
+      e.cc = exact[g].cc;
+      e.opacity = exact[g].opacity;
+      const double ad = alpha_fp64(e, rec[g].x, rec[g].y, ri, rj, alpha_max);
+      if (ad >= alpha_low) prod *= 1.0 - ad;
     }
     g = g_n;
     bx = bx_n;
+    by = by_n;
     g_n = min(raw_nn, n_gauss - 1);
   }
   return wave_prod_f64(prod);
@@ -120,6 +148,12 @@ __device__ __noinline__ double replay_fp64(const RenderRecord* __restrict__ rec,
 // (where its latency would stall the step).
 __device__ __forceinline__ void ready(const float4& v) {
   asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+
+// Makes v available only from here on: nothing computed from it (a store
+// included) is moved above this point, so its load is waited for here.
+__device__ __forceinline__ void from_here(float4& v) {
+  asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
 }
 
 __device__ __forceinline__ void ready(float v) { asm volatile("" ::"v"(v)); }
@@ -271,84 +305,91 @@ __global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(const uint32
 // Per-pixel blend state (Eqs. 2-3) and its load counters.
 struct Pixel {
   float T, cr, cg, cb;
-  float E;          // bound on the relative error of T against its FP64 value
+  float D;          // bound on |T - T_fp64|
   uint32_t nb;      // blended entries (l_blend)
   uint32_t stop_k;  // list position of the entry that stopped the pixel
   uint32_t n_rare;   // FP64 re-decisions (low 16 bits) and replays (high 16 bits)
-  bool done;
 };
 
-// One front-to-back blend of a staged Gaussian (A, B, colour cols[slot]) at the
-// lane's pixel. The FP32 exponent decides alpha >= alpha_low unless it lies
-// within the Gaussian's error band of log2(alpha_low), where FP64 decides.
-// E bounds the relative error of the FP32 transmittance: each blend adds
-// alpha / (1 - alpha) times alpha's relative error (the exponent bound times
-// ln 2, plus the exp2 and rounding error) and one rounding. When T lands
-// within that bound (times 1.5) of t_min, the whole wave recomputes the
-// pixel's transmittance in FP64 over the list so far. Every lane of the wave
-// must call it.
-__device__ __forceinline__ void blend_step(Pixel& px, const float4& A, const float4& B, const float4* cols, int slot,
-                                           uint32_t base, const uint32_t* gids, float fx, float fy, int pi, int pj,
-                                           int lane, uint32_t cap, uint32_t s,
-                                           const RenderRecord* __restrict__ rec,
-                                           const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
-                                           uint32_t n_gauss, const BlendArgs& bl) {
-  const float4 col = cols[slot];  // read now, used at the end of the step
+// One front-to-back blend of the Gaussian staged in slot (A, B, and C: colour
+// and alpha's relative error bound) at the lane's pixel; returns the lanes
+// whose pixel stops at this entry. The FP32
+// exponent decides alpha >= alpha_low unless it lies within the Gaussian's
+// error band of log2(alpha_low), where FP64 decides. D bounds the error of
+// the FP32 transmittance: T' = T (1 - a) carries the old error scaled by
+// (1 - a), plus T a times alpha's relative error (the exponent bound times
+// ln 2, plus the exp2 and rounding error), plus the rounding of T' (counted
+// as 2^-23 T', which also covers the product terms of errors left out). When
+// T lands within 1.5 D (plus t_min's rounding) of t_min, the whole wave
+// recomputes the pixel's transmittance in FP64 over the list so far, and that
+// value decides the stop. A lane that has stopped evaluates only records with
+// exponent -1e30, which change nothing. Every lane of the wave must call it.
+template <bool kCap>
+__device__ __forceinline__ uint64_t blend_step(Pixel& px, const float4& A, const float4& B, const float4& col,
+                                               int slot, uint32_t base, const uint32_t* gids, float fx, float fy,
+                                               int pi, int pj, int lane, uint32_t cap, uint32_t s,
+                                               const RenderRecord* __restrict__ rec,
+                                               const ExactRecord* __restrict__ exact,
+                                               const uint32_t* __restrict__ vals, uint32_t n_gauss,
+                                               const BlendArgs& bl) {
+  // Decisions are kept as wave masks (one bit per lane) so that they combine
+  // with scalar instructions.
   const float q = quad_form(A, B, fx, fy);
   const float e2 = __builtin_amdgcn_exp2f(q);
-  const bool live = !px.done;
-  float a = e2 < bl.alpha_max ? e2 : bl.alpha_max;
-  bool blend = live & (q >= bl.q_low);
-  const bool near_low = live & (fabsf(q - bl.q_low) < B.w);
-  float af = blend ? a : 0.f;
+  float a = __builtin_fminf(e2, bl.alpha_max);
+  uint64_t blend_m = __ballot(q >= bl.q_low);
+  const bool near_low = fabsf(q - bl.q_low) < B.w;
+  float af = __builtin_amdgcn_inverse_ballot_w64(blend_m) ? a : 0.f;
+  float w = af * px.T;
   float Tn = fmaf(-af, px.T, px.T);  // T (1 - alpha) with one rounding
-  const float rel = fmaf(B.w, 0.7f, 0x1p-20f);  // relative error of alpha: band * ln 2 (rounded up) + exp2
-  float En = px.E + (blend ? fmaf(af * __builtin_amdgcn_rcpf(1.f - af), rel, 0x1p-23f) : 0.f);
-  bool near_t = blend & (fabsf(Tn - bl.t_min) < bl.t_min * fmaf(1.5f, En, 0x1p-21f) * bl.t_band);
-  float t_exact = 0.f;
-  bool stop_exact = false;
-  if (__builtin_expect(__ballot(near_low | near_t) != 0, 0)) {
+  float Dn = fmaf(Tn, 0x1p-23f, fmaf(w, col.w, fmaf(-af, px.D, px.D)));
+  uint64_t near_t = blend_m & __ballot(fmaf(-bl.t_err_scale, Dn, fabsf(Tn - bl.t_min)) < bl.t_err_floor);
+  uint64_t stop_fix = 0;  // lanes whose FP64 stop decision differs from the FP32 test of their replayed T
+  if (__builtin_expect((__ballot(near_low) | near_t) != 0, 0)) {
     // Rare (wave-uniform branch): an exponent within its band of
     // log2(alpha_low) is decided in FP64; a transmittance near t_min is
     // recomputed in FP64 by the whole wave over the list so far.
+    const uint64_t low_m = __ballot(near_low);
     if (near_low) {
       const double ad = alpha_fp64_at(rec, exact, gids[slot], pi, pj, bl.alpha_max_d);
-      blend = ad >= bl.alpha_low_d;
-      a = (float)ad;
-      af = blend ? a : 0.f;
+      const bool blend = ad >= bl.alpha_low_d;
+      af = blend ? (float)ad : 0.f;
+      w = af * px.T;
       Tn = fmaf(-af, px.T, px.T);
-      En = px.E + (blend ? fmaf(af * __builtin_amdgcn_rcpf(1.f - af), 0x1p-23f, 0x1p-23f) : 0.f);
-      near_t = blend & (fabsf(Tn - bl.t_min) < bl.t_min * fmaf(1.5f, En, 0x1p-21f) * bl.t_band);
+      Dn = fmaf(Tn, 0x1p-23f, fmaf(w, 0x1p-23f, fmaf(-af, px.D, px.D)));  // alpha rounded from FP64
       px.n_rare += 1u;
     }
-    uint64_t rm = __ballot(near_t);
+    if (low_m) {
+      const uint64_t low_blend = __ballot(near_low & (af > 0.f));
+      blend_m = (blend_m & ~low_m) | low_blend;
+      near_t = (near_t & ~low_m) |
+               (low_blend & __ballot(fmaf(-bl.t_err_scale, Dn, fabsf(Tn - bl.t_min)) < bl.t_err_floor));
+    }
+    uint64_t rm = near_t;
     while (rm) {
       const int L = __builtin_ctzll(rm);
       rm &= rm - 1;
       const int ri = __builtin_amdgcn_readlane(pi, L), rj = __builtin_amdgcn_readlane(pj, L);
       const uint32_t k_now = base + (uint32_t)__builtin_amdgcn_readlane(slot, L);
-      const double prod = replay_fp64(rec, exact, vals, n_gauss, s, k_now, ri, rj, lane, bl);
+      const double prod = replay_fp64(rec, exact, vals, n_gauss, s, k_now, ri, rj, lane, bl);  // same in all lanes
+      stop_fix |= __ballot((prod < bl.t_min_d) != ((float)prod < bl.t_min)) & (1ull << L);
       if (lane == L) {
-        t_exact = (float)prod;
-        stop_exact = prod < bl.t_min_d;
+        Tn = (float)prod;
+        Dn = Tn * 0x1p-24f;  // only the rounding to float remains
         px.n_rare += 1u << 16;
       }
     }
   }
-  const float w = af * px.T;
   px.cr = fmaf(col.x, w, px.cr);
   px.cg = fmaf(col.y, w, px.cg);
   px.cb = fmaf(col.z, w, px.cb);
-  px.T = near_t ? t_exact : Tn;
-  px.E = near_t ? 0x1p-24f : En;  // after a replay only the rounding to float remains
-  px.nb += blend ? 1u : 0u;
-  // bitwise on purpose: no short-circuit branches in the common path
-  const bool t_stop = near_t ? stop_exact : (px.T < bl.t_min);
-  const bool stop = blend & (t_stop | (px.nb == cap));
-  px.stop_k = stop ? base + (uint32_t)slot : px.stop_k;
-  px.done = px.done | stop;
+  px.T = Tn;
+  px.D = Dn;
+  px.nb += __builtin_amdgcn_inverse_ballot_w64(blend_m) ? 1u : 0u;
+  return blend_m & ((__ballot(Tn < bl.t_min) ^ stop_fix) | (kCap ? __ballot(px.nb == cap) : 0ull));
 }
 
+template <bool kCap>
 __global__ void __launch_bounds__(256, 4) render_kernel(
     const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, uint32_t n_pairs, uint32_t n_gauss,
@@ -399,12 +440,12 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
   const uint32_t s = min(ranges[2 * tile], e);
   Pixel px;
   px.T = 1.f;
-  px.E = 0.f;
+  px.D = 0.f;
   px.cr = px.cg = px.cb = 0.f;
   px.nb = 0;
   px.stop_k = 0xffffffffu;
   px.n_rare = 0;
-  px.done = !inside;
+  bool done = !inside;
   const uint32_t cap = bl.lb_cap > 0 ? (uint32_t)bl.lb_cap : 0xffffffffu;
   // The longest lists bound the kernel's duration: let their waves issue
   // first on a shared SIMD (wave priority only; no effect on results).
@@ -448,7 +489,7 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
       my_gid[lane] = g_b;
     }
     // colours are needed only by phase 2: their load overlaps phase 1
-    const float4 col_b = *reinterpret_cast<const float4*>(&rec[((any >> lane) & 1ull) ? g_b : 0u].r);
+    float4 col_b = *reinterpret_cast<const float4*>(&rec[((any >> lane) & 1ull) ? g_b : 0u].r);
     // the sub-block's entries of this batch, in list order: the set bits
     const int n_iter = max(max(__popcll(hm.m[0]), __popcll(hm.m[1])), max(__popcll(hm.m[2]), __popcll(hm.m[3])));
     // issue the next batches' loads before evaluating this one
@@ -507,50 +548,76 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
         ready(B0);
       }
     }
-    if ((any >> lane) & 1ull) my_col[lane] = col_b;
+    from_here(col_b);  // (not merged into the staging above, which would wait for the load there)
+    if ((any >> lane) & 1ull) {
+      // w: alpha's relative error bound, the band times ln 2 (rounded up) plus
+      // the exp2 error; 1 stands for an unbounded one (those Gaussians are
+      // decided in FP64 wherever they are finite, so it never enters D)
+      col_b.w = __builtin_fminf(fmaf(bl.exact ? col_b.w + bl.band_floor : 0.f, 0.7f, 0x1p-20f), 1.f);
+      my_col[lane] = col_b;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // Phase 2, blending: each lane walks its candidates in slot order, which
     // is list (depth) order, with the exact decision logic; two register
     // sets alternate as above. The wave steps while any lane has candidates
-    // left; a lane that stops drops its remaining ones.
+    // left. A lane that stops drops its remaining ones and turns the record
+    // already read for its next step into a no-op (exponent -1e30).
     {
-      uint64_t cm = px.done ? 0ull : cand;
+      uint64_t cm = done ? 0ull : cand;
       int s0 = next_slot(cm), s1 = next_slot(cm);
       float4 A0 = my[s0].a, B0 = my[s0].b, A1, B1;
       ready(A0);
       ready(B0);
 #pragma unroll 1
       while (__ballot(s0 != 64) != 0) {
+        const float4 C0 = my_col[s0];  // read before the next step's record, used within this step
         A1 = my[s1].a;
         B1 = my[s1].b;
         __builtin_amdgcn_sched_barrier(0);
-        blend_step(px, A0, B0, my_col, s0, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
-        if (px.done) {
-          cm = 0;
-          s1 = 64;
-        }
+        uint64_t stop = blend_step<kCap>(px, A0, B0, C0, s0, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals,
+                               n_gauss, bl);
+        const int k0 = s0;
         s0 = next_slot(cm);
         __builtin_amdgcn_sched_barrier(0);
         ready(A1);
         ready(B1);
+        if (__builtin_expect(stop != 0, 0)) {
+          if (__builtin_amdgcn_inverse_ballot_w64(stop)) {
+            px.stop_k = base + (uint32_t)k0;
+            done = true;
+            cm = 0;
+            s0 = 64;
+            s1 = 64;
+            B1.z = -1e30f;
+          }
+        }
         if (__ballot(s1 != 64) == 0) break;
+        const float4 C1 = my_col[s1];
         A0 = my[s0].a;
         B0 = my[s0].b;
         __builtin_amdgcn_sched_barrier(0);
-        blend_step(px, A1, B1, my_col, s1, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals, n_gauss, bl);
-        if (px.done) {
-          cm = 0;
-          s0 = 64;
-        }
+        stop = blend_step<kCap>(px, A1, B1, C1, s1, base, my_gid, fx, fy, pi, pj, lane, cap, s, rec, exact, vals,
+                          n_gauss, bl);
+        const int k1 = s1;
         s1 = next_slot(cm);
         __builtin_amdgcn_sched_barrier(0);
         ready(A0);
         ready(B0);
+        if (__builtin_expect(stop != 0, 0)) {
+          if (__builtin_amdgcn_inverse_ballot_w64(stop)) {
+            px.stop_k = base + (uint32_t)k1;
+            done = true;
+            cm = 0;
+            s0 = 64;
+            s1 = 64;
+            B0.z = -1e30f;
+          }
         }
+      }
     }
-    if (__ballot(!px.done) == 0) goto finished;
+    if (__ballot(!done) == 0) goto finished;
     __builtin_amdgcn_wave_barrier();  // all reads of this batch's slots before the next writes
   }
 finished:
@@ -633,7 +700,8 @@ hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, cons
                          hipStream_t stream) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   ulonglong4* ws4 = out->load_sums ? (ulonglong4*)ws->wave_sums : nullptr;
-  render_kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(
+  auto* kernel = blend.lb_cap > 0 ? render_kernel<true> : render_kernel<false>;
+  kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(
       rec, exact, vals, ranges, order, (uint32_t)n_pairs, (uint32_t)(n_gauss > 0 ? n_gauss : 1), cam, blend,
       n_tiles, out->image, out->final_t, out->l_iter, out->l_blend, ws4, ws->dev_counters);
   return hipGetLastError();
