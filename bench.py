@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=2048)
     ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only"], default=None,
                     help="time one mode only (for profiler runs)")
+    ap.add_argument("--no-alpha-sweep", action="store_true",
+                    help="skip the alpha_low sweep (frames/s and PSNR at 1, 2, 4, 8 / 255)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (scales HBM counters)")
     return ap.parse_args()
@@ -234,6 +236,28 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 10 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         del src, dst
+    # alpha_low sweep (a lossy speed-up the paper allows, Sec. 5.1.2): the
+    # headline AABB frame at larger alpha_low, with its PSNR against the
+    # alpha_low = 1/255 image (both clipped to [0, 1]).
+    alpha_sweep = None
+    if not args.only and not args.no_alpha_sweep:
+        alpha_sweep = []
+        ref_img = images["aabb"].clamp(0.0, 1.0)
+        for k in (1, 2, 4, 8):
+            params = P.RenderParams(cull=P.ADR_CULL_AABB, alpha_low=k / 255.0)
+            for _ in range(args.warmup):
+                P.render(sg, cam, params, ws, **out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                n_pairs = P.render(sg, cam, params, ws, **out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            mse = float(((out["image"].clamp(0.0, 1.0) - ref_img) ** 2).mean())
+            psnr = None if mse == 0.0 else round(10.0 * math.log10(1.0 / mse), 3)
+            alpha_sweep.append({"alpha_low": f"{k}/255", "fps": round(args.steps / dt, 2), "pairs": int(n_pairs),
+                                "psnr_db_vs_1_255": psnr, "identical_to_1_255": mse == 0.0})
+            log(f"alpha_low {k}/255: {args.steps / dt:.1f} frames/s, pairs {n_pairs}, PSNR {psnr}")
     if args.only:
         r = results[args.only]
         print(json.dumps({"mode": args.only, "fps": round(r["fps"], 2), "pairs": r["pairs"],
@@ -305,6 +329,7 @@ def main():
         "speedup_aabb_vs_3sigma": round(results["aabb"]["fps"] / results["3sigma"]["fps"], 4),
         "speedup_adaptive_vs_3sigma": round(results["adaptive"]["fps"] / results["3sigma"]["fps"], 4),
         "identical_output_across_modes": identical,
+        "alpha_low_sweep": alpha_sweep,
         "stages": per_stage,
         "hbm_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "load_imbalance_E_exec_over_E_alg": results["aabb"].get("load_imbalance_E_exec_over_E_alg"),

@@ -216,7 +216,6 @@ __device__ __forceinline__ Fetched fetch(const RenderRecord* __restrict__ rec, u
 // short ones fill in around them. Buckets of floor(log2(length)), longest
 // bucket first; the order inside a bucket does not affect any output.
 constexpr int kOrderBuckets = 33;
-constexpr uint32_t kLongList = 1024;
 
 __device__ __forceinline__ int order_bucket(const uint32_t* __restrict__ ranges, int t, uint32_t n_pairs) {
   const uint32_t e = min(ranges[2 * t + 1], n_pairs), s = min(ranges[2 * t], e);
@@ -447,9 +446,21 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
   px.n_rare = 0;
   bool done = !inside;
   const uint32_t cap = bl.lb_cap > 0 ? (uint32_t)bl.lb_cap : 0xffffffffu;
-  // The longest lists bound the kernel's duration: let their waves issue
-  // first on a shared SIMD (wave priority only; no effect on results).
-  if (e - s >= kLongList) __builtin_amdgcn_s_setprio(3);
+  // The longest lists bound the kernel's duration: on a shared SIMD, waves
+  // issue in order of their list's length relative to the frame's longest
+  // (the first tile of the order): at least 3/4, 1/2, 1/4 of it. Wave
+  // priority only; no effect on results.
+  {
+    const int t0 = (int)min(order[0], (uint32_t)(n_tiles - 1));
+    const uint32_t e0 = min(ranges[2 * t0 + 1], n_pairs), s0 = min(ranges[2 * t0], e0);
+    const uint64_t len0 = e0 - s0, len = e - s;
+    if (len * 4 >= len0 * 3)
+      __builtin_amdgcn_s_setprio(3);
+    else if (len * 2 >= len0)
+      __builtin_amdgcn_s_setprio(2);
+    else if (len * 4 >= len0)
+      __builtin_amdgcn_s_setprio(1);
+  }
 
   // Batches of 64 list entries, software-pipelined: while batch b is
   // evaluated, the records of batch b+1's hits, the cull boxes of batch b+2

@@ -105,6 +105,25 @@ def test_small_scene_parity(P, ws, small, mode):
     check_load_sums(g, o)
 
 
+@pytest.mark.parametrize("k", [2, 4, 8])
+def test_alpha_low_sweep_parity(P, ws, small, k):
+    """Larger alpha_low (the lossy speed-up of Sec. 5.1.2): the adaptive and
+    AABB extents shrink with it and the blend skips more entries, and every
+    output still matches the oracle run at the same alpha_low; 3-sigma and
+    AABB give the same image."""
+    s, sg, cam = small
+    a = k / 255.0
+    say(f"small scene 2000 G, 128x128, alpha_low {k}/255")
+    o = O.render_frame(s, cam, oracle_params(2, alpha_low=a))
+    g = gpu_frame(P, ws, sg, cam, 2, alpha_low=a)
+    check_integer_stage(g, o, s.n)
+    check_pixels(g, o)
+    check_load_sums(g, o)
+    g3 = gpu_frame(P, ws, sg, cam, 0, debug=False, alpha_low=a)
+    assert np.array_equal(g3["image"], g["image"])
+    assert np.array_equal(g3["l_blend"], g["l_blend"])
+
+
 @pytest.mark.parametrize("mode", [0, 2], ids=["3sigma", "aabb"])
 def test_needle_scene_parity(P, ws, mode):
     """Long thin Gaussians at every angle (projected axis ratios up to ~2600):
