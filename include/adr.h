@@ -166,8 +166,20 @@ void adr_workspace_destroy(adr_workspace* ws);
 adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
                       adr_frame* out, adr_workspace* ws, void* stream);
 
-/* Gradient of a scalar loss with respect to the scene, given dL/dimage.
- * Not implemented in this version: returns ADR_E_UNSUPPORTED. */
+/* Gradient of a scalar loss L with respect to the scene inputs, given
+ * dl_dimage = dL/dimage (3 x H x W float32, device): the derivative of the
+ * forward definition (Eqs. 2-3 over the blended list entries, Preprocess of
+ * Sec. 3.1) on the piece fixed by the forward's decisions; clamped alpha,
+ * colour channels and EWA slopes pass no derivative.
+ * Differentiates the frame of the last adr_render on ws, which must have had
+ * the same scene, camera and params (ADR_E_INVALID otherwise); fwd is that
+ * call's frame, whose final_t and l_iter are required (each pixel walks its
+ * list back to front from them: nothing else is stored per entry).
+ * grads: caller-owned device arrays in the layout of adr_scene_desc (any may be
+ * NULL to skip it); every element is written (zero for Gaussians behind the
+ * near plane). float32 atomics add the per-pixel contributions, so results
+ * vary in the last bits from call to call. Asynchronous on stream; ws is
+ * used as scratch (40 bytes per Gaussian). */
 adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
                                const adr_frame* fwd, const float* dl_dimage, adr_scene_grads* grads,
                                adr_workspace* ws, void* stream);

@@ -17,6 +17,8 @@ from .binding import (  # noqa: F401
     Server,
     Workspace,
     clock_s,
+    render_backward,
+    render_differentiable,
     load,
     render,
     render_frame,

@@ -7,6 +7,7 @@ does not touch the GPU; loading the library fails loudly if it is not built.
 from __future__ import annotations
 
 import ctypes
+import math
 import dataclasses
 import pathlib
 
@@ -72,6 +73,11 @@ class adr_frame(ctypes.Structure):
                 ("pair_capacity", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
 
 
+class adr_scene_grads(ctypes.Structure):
+    _fields_ = [("d_means", ctypes.c_void_p), ("d_log_scales", ctypes.c_void_p), ("d_quats", ctypes.c_void_p),
+                ("d_opacity_logits", ctypes.c_void_p), ("d_sh", ctypes.c_void_p)]
+
+
 def lib_path() -> pathlib.Path:
     return _LIB_PATH
 
@@ -102,7 +108,7 @@ def load(path=None):
                                ctypes.POINTER(adr_frame), vp, vp]
     lib.adr_render.restype = i32
     lib.adr_render_backward.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
-                                        ctypes.POINTER(adr_frame), vp, vp, vp, vp]
+                                        ctypes.POINTER(adr_frame), vp, ctypes.POINTER(adr_scene_grads), vp, vp]
     lib.adr_render_backward.restype = i32
     lib.adr_workspace_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.adr_workspace_stage_times.restype = i32
@@ -332,6 +338,79 @@ def render_frame(scene: Scene, cam, params: RenderParams, ws: Workspace = None, 
         out["tiles_touched"] = out["tiles_touched"][:scene.n]
     out["workspace"] = ws
     return out
+
+
+def render_backward(scene: Scene, cam, params: RenderParams, ws: Workspace, frame: dict, dl_dimage,
+                    stream=None) -> dict:
+    """adr_render_backward: gradients of L = sum(dl_dimage * image) with
+    respect to the scene inputs, for the frame that the last render() on ws
+    drew from the same scene, camera and params (frame: its outputs; final_t
+    and l_iter are required). Returns float32 device tensors shaped like the
+    scene arrays: means (N, 3), log_scales (N, 3), quats (N, 4),
+    opacity_logits (N,), sh (N, K, 3)."""
+    import torch
+
+    lib = load()
+    n, k = scene.n, (scene.sh_degree + 1) ** 2
+    dev = frame["image"].device
+    grads = dict(means=torch.empty((n, 3), device=dev), log_scales=torch.empty((n, 3), device=dev),
+                 quats=torch.empty((n, 4), device=dev), opacity_logits=torch.empty((n,), device=dev),
+                 sh=torch.empty((n, k, 3), device=dev))
+    dl = dl_dimage.contiguous().float()
+    f = adr_frame()
+    f.image, f.final_t, f.l_iter = _ptr(frame["image"]), _ptr(frame.get("final_t")), _ptr(frame.get("l_iter"))
+    g = adr_scene_grads()
+    g.d_means, g.d_log_scales, g.d_quats = _ptr(grads["means"]), _ptr(grads["log_scales"]), _ptr(grads["quats"])
+    g.d_opacity_logits, g.d_sh = _ptr(grads["opacity_logits"]), _ptr(grads["sh"])
+    c = camera_to_c(cam)
+    p = params.to_c()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(lib.adr_render_backward(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
+                                   ctypes.c_void_p(dl.data_ptr()), ctypes.byref(g), ws.handle,
+                                   ctypes.c_void_p(int(stream))))
+    return grads
+
+
+def _autograd_function():
+    import torch
+
+    class RenderFn(torch.autograd.Function):
+        """image = render(scene inputs); backward through adr_render_backward."""
+
+        @staticmethod
+        def forward(ctx, means, log_scales, quats, opacity_logits, sh, cam, params, ws):
+            scene = Scene(means.detach(), log_scales.detach(), quats.detach(), opacity_logits.detach(),
+                          sh.detach(), int(round(math.sqrt(sh.shape[1]))) - 1)
+            h, w = int(cam.height), int(cam.width)
+            dev = means.device
+            frame = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
+                         l_iter=torch.empty((h, w), dtype=torch.int32, device=dev))
+            render(scene, cam, params, ws, **frame)
+            ctx.state = (scene, cam, params, ws, frame)
+            return frame["image"].clone()
+
+        @staticmethod
+        def backward(ctx, grad_image):
+            scene, cam, params, ws, frame = ctx.state
+            g = render_backward(scene, cam, params, ws, frame, grad_image)
+            return g["means"], g["log_scales"], g["quats"], g["opacity_logits"], g["sh"], None, None, None
+
+    return RenderFn
+
+
+def render_differentiable(means, log_scales, quats, opacity_logits, sh, cam, params: RenderParams,
+                          ws: Workspace = None):
+    """The image as a differentiable function of the scene inputs (torch
+    tensors on the GPU; sh of shape (N, K, 3)). The backward pass must run
+    before ws renders another frame."""
+    global _render_fn
+    if _render_fn is None:
+        _render_fn = _autograd_function()
+    return _render_fn.apply(means, log_scales, quats, opacity_logits, sh, cam, params, ws or Workspace())
+
+
+_render_fn = None
 
 
 def load_stats_from_sums(sums, n_pixels: int):

@@ -150,6 +150,13 @@ struct adr_workspace {
   hipStream_t last_stream = nullptr;
   int64_t last_pairs = 0;
   int32_t last_depth_bits = 0;  // key bits the last frame's depth sort covered
+  // the last frame rendered on this workspace (what adr_render_backward differentiates)
+  const adr_scene* last_scene = nullptr;
+  adr_camera last_cam{};
+  adr_render_params last_params{};
+  const uint32_t* last_vals = nullptr;  // its sorted Gaussian ids
+  float* grad2d = nullptr;              // kGrad2d floats per Gaussian
+  int64_t grad2d_capacity = 0;
 };
 
 namespace adr {
@@ -209,6 +216,15 @@ hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, cons
                          const CamArgs& cam, const BlendArgs& blend, adr_frame* out, adr_workspace* ws,
                          hipStream_t stream);
 hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums, hipStream_t stream);
+// Backward (gradients). Screen-space gradients per Gaussian, kGrad2d floats:
+// d/dx, d/dy, d/d conic (A, B, C), d/d opacity, d/d colour (r, g, b), unused.
+constexpr int kGrad2d = 10;
+hipError_t launch_render_backward(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
+                                  const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
+                                  const BlendArgs& blend, const float* final_t, const uint32_t* l_iter,
+                                  const float* dl_dimage, float* grad2d, hipStream_t stream);
+hipError_t launch_preprocess_backward(const DeviceScene& s, const CamArgs& cam, double lowpass, const float* grad2d,
+                                      const adr_scene_grads& out, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t stream);
 

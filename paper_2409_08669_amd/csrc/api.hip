@@ -217,14 +217,10 @@ static adr_status validate(const adr_scene* scene, const adr_camera* cam, const 
   return validate_render_args(scene, cam, p, out);
 }
 
-extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
-                                 adr_frame* out, adr_workspace* ws, void* stream_ptr) {
-  adr_status st = validate(scene, cam, p, out, ws);
-  if (st != ADR_OK) return st;
-  hipStream_t stream = (hipStream_t)stream_ptr;
-  const DeviceScene& s = scene->d;
-  const int W = cam->width, H = cam->height;
+namespace {
 
+CamArgs camera_args(const adr_camera* cam, const adr_render_params* p) {
+  const int W = cam->width, H = cam->height;
   CamArgs ca{};
   for (int i = 0; i < 3; ++i) {
     for (int j = 0; j < 3; ++j) ca.r[3 * i + j] = cam->world_to_cam[4 * i + j];
@@ -243,15 +239,10 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ca.height = H;
   ca.tiles_x = (W + kTile - 1) / kTile;
   ca.tiles_y = (H + kTile - 1) / kTile;
-  const int64_t n_tiles = (int64_t)ca.tiles_x * ca.tiles_y;
+  return ca;
+}
 
-  CullArgs cu{};
-  cu.mode = p->cull;
-  cu.quad_cull = (p->flags & ADR_FLAG_NO_QUAD_CULL) ? 0 : 1;
-  cu.alpha_low = p->alpha_low;
-  cu.q_low = std::log2(p->alpha_low);
-  cu.lowpass = p->lowpass;
-
+BlendArgs blend_args(const adr_render_params* p) {
   BlendArgs bl{};
   bl.alpha_max = (float)p->alpha_max;
   bl.t_min = (float)p->t_min;
@@ -268,6 +259,30 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   bl.t_min_d = p->t_min;
   for (int c = 0; c < 3; ++c) bl.bg[c] = p->background[c];
   bl.lb_cap = p->lb_cap;
+  return bl;
+}
+
+}  // namespace
+
+extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                 adr_frame* out, adr_workspace* ws, void* stream_ptr) {
+  adr_status st = validate(scene, cam, p, out, ws);
+  if (st != ADR_OK) return st;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  const DeviceScene& s = scene->d;
+  const int W = cam->width, H = cam->height;
+
+  CamArgs ca = camera_args(cam, p);
+  const int64_t n_tiles = (int64_t)ca.tiles_x * ca.tiles_y;
+
+  CullArgs cu{};
+  cu.mode = p->cull;
+  cu.quad_cull = (p->flags & ADR_FLAG_NO_QUAD_CULL) ? 0 : 1;
+  cu.alpha_low = p->alpha_low;
+  cu.q_low = std::log2(p->alpha_low);
+  cu.lowpass = p->lowpass;
+
+  BlendArgs bl = blend_args(p);
 
   if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
   if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;
@@ -367,6 +382,10 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
   ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, n_pairs, s.n, ca, bl, out, ws,
                         stream));
+  ws->last_scene = scene;
+  ws->last_cam = *cam;
+  ws->last_params = *p;
+  ws->last_vals = vals;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[9], stream));
   ADR_HIP(launch_load_sums(ws, (int)n_tiles, out->load_sums, stream));
   if (timing) {
@@ -394,10 +413,51 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   return ADR_OK;
 }
 
-extern "C" adr_status adr_render_backward(const adr_scene*, const adr_camera*, const adr_render_params*,
-                                          const adr_frame*, const float*, adr_scene_grads*, adr_workspace*, void*) {
-  set_error("adr_render_backward: not implemented in this version");
-  return ADR_E_UNSUPPORTED;
+namespace {
+
+bool same_camera(const adr_camera& a, const adr_camera& b) {
+  for (int i = 0; i < 12; ++i)
+    if (a.world_to_cam[i] != b.world_to_cam[i]) return false;
+  return a.fx == b.fx && a.fy == b.fy && a.cx == b.cx && a.cy == b.cy && a.width == b.width &&
+         a.height == b.height && a.near_z == b.near_z;
+}
+
+bool same_params(const adr_render_params& a, const adr_render_params& b) {
+  return a.cull == b.cull && a.lb_cap == b.lb_cap && a.alpha_low == b.alpha_low && a.alpha_max == b.alpha_max &&
+         a.t_min == b.t_min && a.lowpass == b.lowpass && a.ewa_clamp == b.ewa_clamp &&
+         a.background[0] == b.background[0] && a.background[1] == b.background[1] &&
+         a.background[2] == b.background[2] &&
+         (a.flags & ADR_FLAG_NO_EXACT_BAND) == (b.flags & ADR_FLAG_NO_EXACT_BAND);
+}
+
+}  // namespace
+
+extern "C" adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                          const adr_frame* fwd, const float* dl_dimage, adr_scene_grads* grads,
+                                          adr_workspace* ws, void* stream_ptr) {
+  adr_status st = validate(scene, cam, p, fwd, ws);
+  if (st != ADR_OK) return st;
+  if (!dl_dimage || !grads || !fwd->final_t || !fwd->l_iter) {
+    set_error("adr_render_backward: dl_dimage, grads, and the forward frame's final_t and l_iter are required");
+    return ADR_E_INVALID;
+  }
+  if (ws->last_scene != scene || !same_camera(ws->last_cam, *cam) || !same_params(ws->last_params, *p) ||
+      !ws->last_vals) {
+    set_error("adr_render_backward: the last adr_render on this workspace was not this scene, camera and params");
+    return ADR_E_INVALID;
+  }
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  const DeviceScene& s = scene->d;
+  if (s.n == 0) return ADR_OK;
+  if ((st = grow(ws->grad2d, ws->grad2d_capacity, (int64_t)kGrad2d * s.n, "screen-space gradients")) != ADR_OK)
+    return st;
+  ADR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ws->grad2d), 0u, (int64_t)kGrad2d * s.n, stream));
+  CamArgs ca = camera_args(cam, p);
+  BlendArgs bl = blend_args(p);
+  ADR_HIP(launch_render_backward(ws->rec, ws->exact, ws->last_vals, ws->ranges, ws->last_pairs, s.n, ca, bl,
+                                 fwd->final_t, fwd->l_iter, dl_dimage, ws->grad2d, stream));
+  ADR_HIP(launch_preprocess_backward(s, ca, p->lowpass, ws->grad2d, *grads, stream));
+  return ADR_OK;
 }
 
 extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n) {

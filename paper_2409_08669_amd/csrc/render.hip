@@ -691,6 +691,146 @@ __global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// Backward of the blend (Eqs. 2-3)
+// ---------------------------------------------------------------------------
+// For C = sum_k c_k alpha_k T_k + T_N bg over the entries a pixel blended,
+// with L depending on C through g = dL/dC:
+//   dL/dc_k     = g alpha_k T_k
+//   dL/dalpha_k = g . c_k T_k - (g . S_k + T_N g . bg) / (1 - alpha_k),
+//                 S_k = sum_{j > k} c_j alpha_j T_j,
+// and where alpha_k = sigma_k G_k is below its clamp, G_k = exp(power_k),
+// power = -1/2 (A dx^2 + 2 B dx dy + C dy^2), dx = x - i, dy = y - j:
+//   dL/dsigma = dL/dalpha G,  dL/dpower = dL/dalpha alpha,
+//   dL/dx = -dL/dpower (A dx + B dy),  dL/dy = -dL/dpower (B dx + C dy),
+//   dL/dA = -dL/dpower dx^2 / 2,  dL/dB = -dL/dpower dx dy,  dL/dC = -dL/dpower dy^2 / 2.
+// Each pixel walks its tile list back to front from the last entry it
+// examined (l_iter of the forward), recovering T_k = T_{k+1} / (1 - alpha_k)
+// from the final transmittance, so no per-entry state is stored. Which entries
+// it blended is decided exactly as in the forward (the FP32 exponent outside
+// the Gaussian's error band, FP64 inside it). Per list entry the wave adds up
+// its pixels' contributions and one lane adds them to the Gaussian's nine
+// screen-space gradients.
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(256) render_backward_kernel(
+    const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, uint32_t n_pairs, uint32_t n_gauss, CamArgs cam, BlendArgs bl,
+    const float* __restrict__ final_t, const uint32_t* __restrict__ l_iter, const float* __restrict__ dl_dimage,
+    float* __restrict__ grad2d) {
+  __shared__ Staged stage[4][64];
+  __shared__ float4 stage_col[4][64];  // r, g, b, opacity
+  __shared__ float4 stage_con[4][64];  // conic A, B, C, Gaussian id (bits)
+  const int tile = blockIdx.x;
+  const int W = cam.width, H = cam.height;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int qx0 = tx * kTile + (wid & 1) * kQuad;
+  const int qy0 = ty * kTile + (wid >> 1) * kQuad;
+  if (qx0 >= W || qy0 >= H) return;  // wave-uniform
+  const uint32_t e = min(ranges[2 * tile + 1], n_pairs);
+  const uint32_t s = min(ranges[2 * tile], e);
+  if (e <= s) return;
+  const int sb = lane >> 4;
+  const int lx = (sb & 1) * kSub + (lane & 3), ly = (sb >> 1) * kSub + ((lane >> 2) & 3);
+  const int pi = qx0 + lx, pj = qy0 + ly;
+  const bool inside = pi < W && pj < H;
+  const float fx = (float)lx, fy = (float)ly;
+  const int64_t plane = (int64_t)W * H;
+  const int64_t pix = inside ? (int64_t)pj * W + pi : 0;
+  const uint32_t n_ex = inside ? min(l_iter[pix], e - s) : 0u;
+  float T = inside ? final_t[pix] : 1.f;
+  const float g0 = inside ? dl_dimage[pix] : 0.f;
+  const float g1 = inside ? dl_dimage[plane + pix] : 0.f;
+  const float g2 = inside ? dl_dimage[2 * plane + pix] : 0.f;
+  const float bg_t = T * (g0 * bl.bg[0] + g1 * bl.bg[1] + g2 * bl.bg[2]);
+  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
+  uint32_t n_max = n_ex;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) n_max = max(n_max, (uint32_t)__shfl_xor((int)n_max, off, 64));
+  const uint2 kNoBox = make_uint2(1u, 1u);
+  for (int b = ((int)n_max - 1) >> 6; b >= 0; --b) {
+    const uint32_t base = s + 64u * (uint32_t)b;
+    const uint32_t k_lane = base + (uint32_t)lane;
+    const bool valid = k_lane < s + n_max;
+    const uint32_t g = valid ? min(vals[k_lane], n_gauss - 1) : 0u;
+    const SubMasks hm = sub_masks(valid ? load_box(rec, g) : kNoBox, qx0, qy0);
+    const uint64_t any = hm.m[0] | hm.m[1] | hm.m[2] | hm.m[3];
+    if ((any >> lane) & 1ull) {
+      const RenderRecord& r = rec[g];
+      Staged st;
+      st.a = make_float4((float)(r.x - (double)qx0), (float)(r.y - (double)qy0), r.rc, r.rs);
+      st.b = make_float4(r.a1, r.a2, r.ql, bl.exact ? r.dq + bl.band_floor : 0.f);
+      stage[wid][lane] = st;
+      const ExactRecord& ex = exact[g];
+      stage_col[wid][lane] = make_float4(r.r, r.g, r.b, (float)ex.opacity);
+      stage_con[wid][lane] = make_float4((float)ex.ca, (float)ex.cb, (float)ex.cc, __uint_as_float(g));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint64_t my_mask = sb == 0 ? hm.m[0] : sb == 1 ? hm.m[1] : sb == 2 ? hm.m[2] : hm.m[3];
+    uint64_t rem = any;
+    while (rem) {
+      const int k = 63 - (int)__builtin_clzll(rem);  // back to front
+      rem &= ~(1ull << k);
+      const bool act = inside && ((my_mask >> k) & 1ull) && (base + (uint32_t)k < s + n_ex);
+      const float4 A = stage[wid][k].a, B = stage[wid][k].b;
+      const float q = quad_form(A, B, fx, fy);
+      bool blend = act && q >= bl.q_low;
+      const bool near_low = act && fabsf(q - bl.q_low) < B.w;
+      if (__ballot(near_low) != 0ull) {
+        if (near_low) {
+          const uint32_t gk = __float_as_uint(stage_con[wid][k].w);
+          blend = alpha_fp64_at(rec, exact, gk, pi, pj, bl.alpha_max_d) >= bl.alpha_low_d;
+        }
+      }
+      float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (blend) {
+        const float4 col = stage_col[wid][k], con = stage_con[wid][k];
+        const float dx = A.x - fx, dy = A.y - fy;
+        const float power = -0.5f * (con.x * dx * dx + 2.f * con.y * dx * dy + con.z * dy * dy);
+        const float G = __expf(power);
+        const float a_raw = col.w * G;
+        const float a = fminf(a_raw, bl.alpha_max);
+        const float inv = 1.f / (1.f - a);
+        const float Tk = T * inv;
+        const float dl_da = (g0 * col.x + g1 * col.y + g2 * col.z) * Tk - (g0 * S0 + g1 * S1 + g2 * S2 + bg_t) * inv;
+        const float w = a * Tk;
+        d[6] = g0 * w;
+        d[7] = g1 * w;
+        d[8] = g2 * w;
+        S0 = fmaf(col.x, w, S0);
+        S1 = fmaf(col.y, w, S1);
+        S2 = fmaf(col.z, w, S2);
+        T = Tk;
+        if (a_raw < bl.alpha_max) {
+          const float dp = dl_da * a;
+          d[0] = -dp * (con.x * dx + con.y * dy);
+          d[1] = -dp * (con.y * dx + con.z * dy);
+          d[2] = -0.5f * dp * dx * dx;
+          d[3] = -dp * dx * dy;
+          d[4] = -0.5f * dp * dy * dy;
+          d[5] = dl_da * G;
+        }
+      }
+      if (__ballot(blend) != 0ull) {
+        const uint32_t gk = __float_as_uint(stage_con[wid][k].w);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const float v = wave_sum_f32(d[i]);
+          if (lane == 0 && v != 0.f) atomicAdd(&grad2d[(int64_t)gk * kGrad2d + i], v);
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // every read of this batch's slots before the next writes
+  }
+}
+
 }  // namespace
 
 int64_t tile_order_scratch(int n_tiles) { return (int64_t)kOrderBuckets * ((n_tiles + kOrderBlock - 1) / kOrderBlock); }
@@ -728,4 +868,18 @@ hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums,
   return hipGetLastError();
 }
 
+// grad2d: kGrad2d floats per Gaussian, zeroed by the caller
+hipError_t launch_render_backward(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
+                                  const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
+                                  const BlendArgs& blend, const float* final_t, const uint32_t* l_iter,
+                                  const float* dl_dimage, float* grad2d, hipStream_t stream) {
+  const int n_tiles = cam.tiles_x * cam.tiles_y;
+  if (n_tiles <= 0 || n_pairs <= 0 || n_gauss <= 0) return hipSuccess;
+  render_backward_kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(rec, exact, vals, ranges, (uint32_t)n_pairs,
+                                                                      (uint32_t)n_gauss, cam, blend, final_t, l_iter,
+                                                                      dl_dimage, grad2d);
+  return hipGetLastError();
+}
+
 }  // namespace adr
+

@@ -8,6 +8,7 @@ from .scenes import (  # noqa: F401
     Scene,
     Camera,
     scene_small,
+    scene_small_sh3,
     scene_needles,
     scene_clusters,
     scene_heavy,

@@ -77,6 +77,21 @@ def scene_small(n: int = 2000, seed: int = 0) -> Scene:
     return Scene(_f32(means), _f32(log_scales), _f32(quats), _f32(logits), _f32(sh), 0)
 
 
+def scene_small_sh3(n: int = 400, seed: int = 0) -> Scene:
+    """scene_small's layout with larger footprints (centres x 0.6, log-scales
+    + 0.8) and SH degree 3: the DC term holds rgb ~ U[0, 1], the 15 higher
+    coefficients per channel are N(0, 0.3). Float64 arrays, so that finite
+    differences see the exact inputs."""
+    base = scene_small(n, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    sh = np.zeros((n, 16, 3))
+    sh[:, :1, :] = base.sh
+    sh[:, 1:, :] = rng.normal(0.0, 0.3, size=(n, 15, 3))
+    f64 = lambda a: np.asarray(a, dtype=np.float64).copy()
+    return Scene(f64(base.means) * 0.6, f64(base.log_scales) + 0.8, f64(base.quats), f64(base.opacity_logits),
+                 sh, 3)
+
+
 def scene_needles(n: int = 1500, seed: int = 0) -> Scene:
     """Stress scene for the FP32 precision of the blend: means U[-1,1]^3,
     one log-scale N(-1.5,0.5) and two N(-6,0.7) per Gaussian (axis ratios

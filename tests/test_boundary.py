@@ -8,6 +8,8 @@ import re
 import numpy as np
 import pytest
 
+from synth import camera_small
+
 ROOT = pathlib.Path(__file__).resolve().parents[1]
 HEADER = ROOT / "include" / "adr.h"
 
@@ -95,10 +97,20 @@ def test_render_rejects_bad_arguments_on_host():
         binding.ADR_E_INVALID
 
 
-def test_backward_is_declared_and_reports_unsupported():
+def test_backward_rejects_missing_arguments_on_the_host():
+    """adr_render_backward checks its arguments before touching the device:
+    NULL handles, and a forward frame without final_t or l_iter."""
     binding, lib = _lib()
-    assert lib.adr_render_backward(None, None, None, None, None, None, None, None) == binding.ADR_E_UNSUPPORTED
-    assert "not implemented" in binding.last_error()
+    assert lib.adr_render_backward(None, None, None, None, None, None, None, None) == binding.ADR_E_INVALID
+    fake = ctypes.c_void_p(1)
+    cam = binding.camera_to_c(camera_small(32, 32))
+    p = binding.RenderParams().to_c()
+    f = binding.adr_frame()
+    f.image = 1  # a forward frame with an image but neither final_t nor l_iter
+    g = binding.adr_scene_grads()
+    assert lib.adr_render_backward(fake, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f), fake,
+                                   ctypes.byref(g), fake, None) == binding.ADR_E_INVALID
+    assert "final_t and l_iter" in binding.last_error()
 
 
 def test_stage_times_and_counters_without_frames():

@@ -10,22 +10,13 @@ import pytest
 
 import oracle as O
 from oracle import adr_grad as G
-from synth import Scene, scene_small, camera_small
+from synth import Scene, scene_small_sh3, camera_small
 
 KEYS = ("means", "log_scales", "quats", "opacity_logits", "sh")
 
 
 def sh3_scene(n, seed):
-    """A small degree-3 scene: scene_small's layout with random higher-order
-    coefficients, in float64 so that finite differences see exact inputs."""
-    s = scene_small(n, seed=seed)
-    rng = np.random.default_rng(seed + 100)
-    sh = np.zeros((n, 16, 3))
-    sh[:, :1, :] = s.sh
-    sh[:, 1:, :] = rng.normal(0.0, 0.3, size=(n, 15, 3))
-    f64 = lambda a: np.asarray(a, dtype=np.float64).copy()
-    # larger footprints than scene_small so that a small image has overlaps
-    return Scene(f64(s.means) * 0.6, f64(s.log_scales) + 0.8, f64(s.quats), f64(s.opacity_logits), sh, 3)
+    return scene_small_sh3(n, seed=seed)
 
 
 def perturbed(scene, key, idx, h):
