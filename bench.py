@@ -56,6 +56,8 @@ def parse():
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
                     help="skip the alpha_low sweep (frames/s and PSNR at 1, 2, 4, 8 / 255)")
+    ap.add_argument("--no-backward", action="store_true",
+                    help="skip the gradient timing (adr_render_backward on the AABB frame)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (scales HBM counters)")
     return ap.parse_args()
@@ -258,6 +260,35 @@ def main():
             alpha_sweep.append({"alpha_low": f"{k}/255", "fps": round(args.steps / dt, 2), "pairs": int(n_pairs),
                                 "psnr_db_vs_1_255": psnr, "identical_to_1_255": mse == 0.0})
             log(f"alpha_low {k}/255: {args.steps / dt:.1f} frames/s, pairs {n_pairs}, PSNR {psnr}")
+    # Gradients (next row 2): adr_render_backward of the AABB frame for a
+    # seeded dL/dimage, timed alone (the same forward differentiated again)
+    # and as forward + backward back to back.
+    backward = None
+    if not args.only and not args.no_backward:
+        params = P.RenderParams(cull=P.ADR_CULL_AABB)
+        frame = {k: out[k] for k in ("image", "final_t", "l_iter")}
+        gen = torch.Generator(device=dev).manual_seed(args.seed)
+        dl = torch.randn((3, h, w), device=dev, generator=gen)
+        for _ in range(max(args.warmup // 2, 1)):
+            P.render(sg, cam, params, ws, **out)
+            P.render_backward(sg, cam, params, ws, frame, dl)
+        torch.cuda.synchronize()
+        nb = max(args.steps // 2, 1)
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            P.render(sg, cam, params, ws, **out)
+            g = P.render_backward(sg, cam, params, ws, frame, dl)
+        torch.cuda.synchronize()
+        fwd_bwd = (time.perf_counter() - t0) / nb
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            g = P.render_backward(sg, cam, params, ws, frame, dl)
+        torch.cuda.synchronize()
+        bwd = (time.perf_counter() - t0) / nb
+        backward = {"ms_backward": round(bwd * 1e3, 4), "ms_forward_plus_backward": round(fwd_bwd * 1e3, 4),
+                    "frames_per_s_forward_plus_backward": round(1.0 / fwd_bwd, 2),
+                    "grad_abs_max": {k: float(v.abs().max()) for k, v in g.items()}}
+        log(f"backward: {bwd * 1e3:.3f} ms alone, forward + backward {fwd_bwd * 1e3:.3f} ms")
     if args.only:
         r = results[args.only]
         print(json.dumps({"mode": args.only, "fps": round(r["fps"], 2), "pairs": r["pairs"],
@@ -330,6 +361,7 @@ def main():
         "speedup_adaptive_vs_3sigma": round(results["adaptive"]["fps"] / results["3sigma"]["fps"], 4),
         "identical_output_across_modes": identical,
         "alpha_low_sweep": alpha_sweep,
+        "backward": backward,
         "stages": per_stage,
         "hbm_copy_GBs": round(copy_gbs, 1) if copy_gbs else None,
         "load_imbalance_E_exec_over_E_alg": results["aabb"].get("load_imbalance_E_exec_over_E_alg"),
