@@ -434,7 +434,8 @@ static ShConsts make_sh_consts() {
 // ---------------------------------------------------------------------------
 // Backward of Preprocess: from the screen-space gradients of a Gaussian (its
 // centre x, y, conic A, B, C, opacity and colour) to its inputs, by the chain
-// rule through the forward's steps in reverse, in FP64:
+// rule through the forward's steps in reverse, in FP32 (the forward's FP64
+// decisions are not retaken here, so FP32 is accurate enough):
 //   colour  c = max(0, sum_k K_k Y_k(v) sh_k + 1/2), v = unit(mean - camera):
 //           d sh_k = dc K_k Y_k, dv = sum_k dc . sh_k K_k grad Y_k, projected
 //           onto the tangent plane and divided by |mean - camera|;
@@ -446,177 +447,242 @@ static ShConsts make_sh_consts() {
 //   x, y    = f p_{x,y}/p_z + c - 1/2;  p = W mean + t;
 //   Sigma   = M M^T, M = R(q / |q|) diag(exp(log_scale)).
 // Gaussians behind the near plane or with a degenerate Sigma' get zeros.
+template <int K>
 __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
-    const float* __restrict__ planes, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, double lowpass,
+    const float* __restrict__ planes, int64_t n, ShConsts shc, CamArgs cam, double lowpass,
     const float* __restrict__ grad2d, float* __restrict__ d_means, float* __restrict__ d_log_scales,
     float* __restrict__ d_quats, float* __restrict__ d_logits, float* __restrict__ d_sh) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
+  using real = float;  // gradients need ~1e-4 relative accuracy: FP32 throughout
+  const real cfx = (real)cam.fx, cfy = (real)cam.fy, clim_x = (real)cam.lim_x, clim_y = (real)cam.lim_y;
+  const real ct[3] = {(real)cam.t[0], (real)cam.t[1], (real)cam.t[2]};
+  const real cpos[3] = {(real)cam.cam_pos[0], (real)cam.cam_pos[1], (real)cam.cam_pos[2]};
+  const real lp = (real)lowpass;
+  // the workgroup's SH gradients, written out together (one row of 3K floats
+  // per Gaussian would otherwise make every store touch 64 cache lines)
+  __shared__ float sh_out[256 * 3 * K];
+  const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t g = g0 + threadIdx.x;
+  const int64_t n_here = min((int64_t)blockDim.x, n - g0);
+  float* my_sh = sh_out + threadIdx.x * 3 * K;
+#pragma unroll
+  for (int i = 0; i < 3 * K; ++i) my_sh[i] = 0.f;
+  if (g < n) {
   const float4 ga = geo_a[g], gb = geo_b[g], gq = geo_q[g];
-  const double mx = ga.x, my = ga.y, mz = ga.z;
-  const double* W = cam.r;
-  const double px = W[0] * mx + W[1] * my + W[2] * mz + cam.t[0];
-  const double py = W[3] * mx + W[4] * my + W[5] * mz + cam.t[1];
-  const double pz = W[6] * mx + W[7] * my + W[8] * mz + cam.t[2];
-  double dm[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dlogit = 0;
-  bool live = pz > cam.near_z;
+  const real mx = ga.x, my = ga.y, mz = ga.z;
+  real W[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) W[i] = (real)cam.r[i];
+  const real px = W[0] * mx + W[1] * my + W[2] * mz + ct[0];
+  const real py = W[3] * mx + W[4] * my + W[5] * mz + ct[1];
+  const real pz = W[6] * mx + W[7] * my + W[8] * mz + ct[2];
+  real dm[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dlogit = 0;
+  bool live = pz > (real)cam.near_z;
   // forward, as in Preprocess
-  const double sc[3] = {exp((double)gb.x), exp((double)gb.y), exp((double)gb.z)};
-  const double qn2 = (double)gq.x * gq.x + (double)gq.y * gq.y + (double)gq.z * gq.z + (double)gq.w * gq.w;
-  const double qn = 1.0 / sqrt(qn2);
-  const double qw = gq.x * qn, qx = gq.y * qn, qy = gq.z * qn, qz = gq.w * qn;
-  double R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+  const real sc[3] = {exp((real)gb.x), exp((real)gb.y), exp((real)gb.z)};
+  const real qn2 = (real)gq.x * gq.x + (real)gq.y * gq.y + (real)gq.z * gq.z + (real)gq.w * gq.w;
+  const real qn = 1.0f / sqrt(qn2);
+  const real qw = gq.x * qn, qx = gq.y * qn, qy = gq.z * qn, qz = gq.w * qn;
+  real R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
                     {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
                     {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-  double M[3][3], Sg[3][3];
+  real M[3][3], Sg[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sc[j];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Sg[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
-  const double z = live ? pz : 1.0;
-  const double rx = px / z, ry = py / z;
-  const bool cx_free = rx > -cam.lim_x && rx < cam.lim_x, cy_free = ry > -cam.lim_y && ry < cam.lim_y;
-  const double xt = z * fmin(fmax(rx, -cam.lim_x), cam.lim_x);
-  const double yt = z * fmin(fmax(ry, -cam.lim_y), cam.lim_y);
-  const double j00 = cam.fx / z, j02 = -cam.fx * xt / (z * z);
-  const double j11 = cam.fy / z, j12 = -cam.fy * yt / (z * z);
-  double T[2][3];
+  const real z = live ? pz : 1.0f;
+  const real rx = px / z, ry = py / z;
+  const bool cx_free = rx > -clim_x && rx < clim_x, cy_free = ry > -clim_y && ry < clim_y;
+  const real xt = z * fmin(fmax(rx, -clim_x), clim_x);
+  const real yt = z * fmin(fmax(ry, -clim_y), clim_y);
+  const real j00 = cfx / z, j02 = -cfx * xt / (z * z);
+  const real j11 = cfy / z, j12 = -cfy * yt / (z * z);
+  real T[2][3];
   for (int k = 0; k < 3; ++k) {
     T[0][k] = j00 * W[k] + j02 * W[6 + k];
     T[1][k] = j11 * W[3 + k] + j12 * W[6 + k];
   }
-  double TS[2][3];  // T Sigma
+  real TS[2][3];  // T Sigma
   for (int i = 0; i < 2; ++i)
     for (int k = 0; k < 3; ++k) TS[i][k] = T[i][0] * Sg[0][k] + T[i][1] * Sg[1][k] + T[i][2] * Sg[2][k];
-  const double a = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + lowpass;
-  const double b = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
-  const double c = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + lowpass;
-  const double det = a * c - b * b;
-  live = live && det > 0.0;
-  const int K = n_coeff;
+  const real a = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + lp;
+  const real b = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+  const real c = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + lp;
+  const real det = a * c - b * b;
+  live = live && det > 0.0f;
   if (live) {
     const float* gr = grad2d + g * kGrad2d;
-    const double gx = gr[0], gy = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], gO = gr[5];
-    double gcol[3] = {gr[6], gr[7], gr[8]};
+    const real gx = gr[0], gy = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], gO = gr[5];
+    real gcol[3] = {gr[6], gr[7], gr[8]};
     // opacity
-    const double op = 1.0 / (1.0 + exp(-(double)ga.w));
-    dlogit = gO * op * (1.0 - op);
+    const real op = 1.0f / (1.0f + exp(-(real)ga.w));
+    dlogit = gO * op * (1.0f - op);
     // colour (SH basis polynomials of the forward, and their gradients)
-    double vx = mx - cam.cam_pos[0], vy = my - cam.cam_pos[1], vz = mz - cam.cam_pos[2];
-    const double vlen = sqrt(vx * vx + vy * vy + vz * vz);
+    real vx = mx - cpos[0], vy = my - cpos[1], vz = mz - cpos[2];
+    const real vlen = sqrt(vx * vx + vy * vy + vz * vz);
     vx /= vlen;
     vy /= vlen;
     vz /= vlen;
-    double Y[16], dY[16][3];
-    for (int k = 0; k < 16; ++k) Y[k] = dY[k][0] = dY[k][1] = dY[k][2] = 0.0;
-    const double x = vx, y = vy, zz = vz;
-    Y[0] = 1.0;
-    Y[1] = -y;  dY[1][1] = -1.0;
-    Y[2] = zz;  dY[2][2] = 1.0;
-    Y[3] = -x;  dY[3][0] = -1.0;
-    Y[4] = 6 * x * y;  dY[4][0] = 6 * y;  dY[4][1] = 6 * x;
-    Y[5] = -3 * zz * y;  dY[5][1] = -3 * zz;  dY[5][2] = -3 * y;
-    Y[6] = 0.5 * (3 * zz * zz - 1);  dY[6][2] = 3 * zz;
-    Y[7] = -3 * zz * x;  dY[7][0] = -3 * zz;  dY[7][2] = -3 * x;
-    Y[8] = 3 * (x * x - y * y);  dY[8][0] = 6 * x;  dY[8][1] = -6 * y;
-    const double t = -1.5 * (5 * zz * zz - 1), dt = -15 * zz;
-    Y[9] = -15 * (3 * x * x * y - y * y * y);  dY[9][0] = -90 * x * y;  dY[9][1] = -45 * x * x + 45 * y * y;
-    Y[10] = 30 * x * y * zz;  dY[10][0] = 30 * y * zz;  dY[10][1] = 30 * x * zz;  dY[10][2] = 30 * x * y;
-    Y[11] = t * y;  dY[11][1] = t;  dY[11][2] = dt * y;
-    Y[12] = 0.5 * (5 * zz * zz * zz - 3 * zz);  dY[12][2] = 0.5 * (15 * zz * zz - 3);
-    Y[13] = t * x;  dY[13][0] = t;  dY[13][2] = dt * x;
-    Y[14] = 15 * zz * (x * x - y * y);  dY[14][0] = 30 * x * zz;  dY[14][1] = -30 * y * zz;
-    dY[14][2] = 15 * (x * x - y * y);
-    Y[15] = -15 * (x * x * x - 3 * x * y * y);  dY[15][0] = -45 * x * x + 45 * y * y;  dY[15][1] = 90 * x * y;
-    double raw[3] = {0.5, 0.5, 0.5};
-    for (int k = 0; k < K; ++k)
-      for (int ch = 0; ch < 3; ++ch) raw[ch] += (double)shc.k[k] * Y[k] * planes[(int64_t)(3 * k + ch) * n + g];
-    for (int ch = 0; ch < 3; ++ch)
-      if (raw[ch] < 0.0) gcol[ch] = 0.0;  // clamped channel
-    double dv[3] = {0, 0, 0};
-    for (int k = 0; k < K; ++k) {
-      double acc = 0.0;
-      for (int ch = 0; ch < 3; ++ch) {
-        const double coef = planes[(int64_t)(3 * k + ch) * n + g];
-        acc += gcol[ch] * coef;
-        if (d_sh) d_sh[(g * K + k) * 3 + ch] = (float)(gcol[ch] * shc.k[k] * Y[k]);
-      }
-      for (int i = 0; i < 3; ++i) dv[i] += acc * shc.k[k] * dY[k][i];
+    // basis polynomials of the forward (Condon-Shortley phase); only the first K
+    const real x = vx, y = vy, zz = vz;
+    real Y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) Y[k] = 0.0f;
+    Y[0] = 1.0f;
+    const real t = -1.5f * (5 * zz * zz - 1), dt = -15 * zz;
+    if (K > 1) {
+      Y[1] = -y;
+      Y[2] = zz;
+      Y[3] = -x;
     }
-    const double vdot = dv[0] * vx + dv[1] * vy + dv[2] * vz;
+    if (K > 4) {
+      Y[4] = 6 * x * y;
+      Y[5] = -3 * zz * y;
+      Y[6] = 0.5f * (3 * zz * zz - 1);
+      Y[7] = -3 * zz * x;
+      Y[8] = 3 * (x * x - y * y);
+    }
+    if (K > 9) {
+      Y[9] = -15 * (3 * x * x * y - y * y * y);
+      Y[10] = 30 * x * y * zz;
+      Y[11] = t * y;
+      Y[12] = 0.5f * (5 * zz * zz * zz - 3 * zz);
+      Y[13] = t * x;
+      Y[14] = 15 * zz * (x * x - y * y);
+      Y[15] = -15 * (x * x * x - 3 * x * y * y);
+    }
+    float coef[3 * K];  // all SH loads issued together
+#pragma unroll
+    for (int i = 0; i < 3 * K; ++i) coef[i] = planes[(int64_t)i * n + g];
+    real raw[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) raw[ch] += (real)shc.k[k] * Y[k] * coef[3 * k + ch];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+      if (raw[ch] < 0.0f) gcol[ch] = 0.0f;  // clamped channel
+    // wk = K_k (dc . sh_k): the weight of basis k's gradient in dL/dv
+    real wk[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) wk[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      real acc = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        acc += gcol[ch] * coef[3 * k + ch];
+        my_sh[3 * k + ch] = (float)(gcol[ch] * shc.k[k] * Y[k]);
+      }
+      wk[k] = acc * shc.k[k];
+    }
+    // dL/dv = sum_k wk grad Y_k (gradients of the polynomials in x, y, z)
+    real dv[3] = {0, 0, 0};
+    if (K > 1) {
+      dv[1] -= wk[1];
+      dv[2] += wk[2];
+      dv[0] -= wk[3];
+    }
+    if (K > 4) {
+      dv[0] += 6 * y * wk[4];
+      dv[1] += 6 * x * wk[4];
+      dv[1] -= 3 * zz * wk[5];
+      dv[2] -= 3 * y * wk[5];
+      dv[2] += 3 * zz * wk[6];
+      dv[0] -= 3 * zz * wk[7];
+      dv[2] -= 3 * x * wk[7];
+      dv[0] += 6 * x * wk[8];
+      dv[1] -= 6 * y * wk[8];
+    }
+    if (K > 9) {
+      dv[0] -= 90 * x * y * wk[9];
+      dv[1] += (-45 * x * x + 45 * y * y) * wk[9];
+      dv[0] += 30 * y * zz * wk[10];
+      dv[1] += 30 * x * zz * wk[10];
+      dv[2] += 30 * x * y * wk[10];
+      dv[1] += t * wk[11];
+      dv[2] += dt * y * wk[11];
+      dv[2] += 0.5f * (15 * zz * zz - 3) * wk[12];
+      dv[0] += t * wk[13];
+      dv[2] += dt * x * wk[13];
+      dv[0] += 30 * x * zz * wk[14];
+      dv[1] -= 30 * y * zz * wk[14];
+      dv[2] += 15 * (x * x - y * y) * wk[14];
+      dv[0] += (-45 * x * x + 45 * y * y) * wk[15];
+      dv[1] += 90 * x * y * wk[15];
+    }
+    const real vdot = dv[0] * vx + dv[1] * vy + dv[2] * vz;
     dm[0] += (dv[0] - vdot * vx) / vlen;
     dm[1] += (dv[1] - vdot * vy) / vlen;
     dm[2] += (dv[2] - vdot * vz) / vlen;
     // conic N = M^-1: dM = -N dN N, with dN = [[gA, gB/2], [gB/2, gC]]
-    const double NA = c / det, NB = -b / det, NC = a / det;
-    const double P00 = NA * gA + NB * 0.5 * gB, P01 = NA * 0.5 * gB + NB * gC;
-    const double P10 = NB * gA + NC * 0.5 * gB, P11 = NB * 0.5 * gB + NC * gC;
-    const double da = -(P00 * NA + P01 * NB);
-    const double db = -2.0 * (P00 * NB + P01 * NC);
-    const double dc = -(P10 * NB + P11 * NC);
+    const real NA = c / det, NB = -b / det, NC = a / det;
+    const real P00 = NA * gA + NB * 0.5f * gB, P01 = NA * 0.5f * gB + NB * gC;
+    const real P10 = NB * gA + NC * 0.5f * gB, P11 = NB * 0.5f * gB + NC * gC;
+    const real da = -(P00 * NA + P01 * NB);
+    const real db = -2.0f * (P00 * NB + P01 * NC);
+    const real dc = -(P10 * NB + P11 * NC);
     // Sigma' = T Sigma T^T: G = [[da, db/2], [db/2, dc]]
-    const double G[2][2] = {{da, 0.5 * db}, {0.5 * db, dc}};
-    double dS[3][3], dT[2][3];
+    const real G[2][2] = {{da, 0.5f * db}, {0.5f * db, dc}};
+    real dS[3][3], dT[2][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        double acc = 0.0;
+        real acc = 0.0f;
         for (int u = 0; u < 2; ++u)
           for (int v = 0; v < 2; ++v) acc += T[u][i] * G[u][v] * T[v][j];
         dS[i][j] = acc;
       }
     for (int u = 0; u < 2; ++u)
-      for (int k = 0; k < 3; ++k) dT[u][k] = 2.0 * (G[u][0] * TS[0][k] + G[u][1] * TS[1][k]);
+      for (int k = 0; k < 3; ++k) dT[u][k] = 2.0f * (G[u][0] * TS[0][k] + G[u][1] * TS[1][k]);
     // T = J W
-    const double dj00 = dT[0][0] * W[0] + dT[0][1] * W[1] + dT[0][2] * W[2];
-    const double dj02 = dT[0][0] * W[6] + dT[0][1] * W[7] + dT[0][2] * W[8];
-    const double dj11 = dT[1][0] * W[3] + dT[1][1] * W[4] + dT[1][2] * W[5];
-    const double dj12 = dT[1][0] * W[6] + dT[1][1] * W[7] + dT[1][2] * W[8];
-    double dpx = 0.0, dpy = 0.0, dpz = 0.0;
-    dpz += -dj00 * cam.fx / (z * z) - dj11 * cam.fy / (z * z);
+    const real dj00 = dT[0][0] * W[0] + dT[0][1] * W[1] + dT[0][2] * W[2];
+    const real dj02 = dT[0][0] * W[6] + dT[0][1] * W[7] + dT[0][2] * W[8];
+    const real dj11 = dT[1][0] * W[3] + dT[1][1] * W[4] + dT[1][2] * W[5];
+    const real dj12 = dT[1][0] * W[6] + dT[1][1] * W[7] + dT[1][2] * W[8];
+    real dpx = 0.0f, dpy = 0.0f, dpz = 0.0f;
+    dpz += -dj00 * cfx / (z * z) - dj11 * cfy / (z * z);
     if (cx_free) {  // j02 = -fx px / z^2
-      dpx += -dj02 * cam.fx / (z * z);
-      dpz += dj02 * 2.0 * cam.fx * px / (z * z * z);
+      dpx += -dj02 * cfx / (z * z);
+      dpz += dj02 * 2.0f * cfx * px / (z * z * z);
     } else {  // j02 = -fx L / z, L = +-lim_x
-      dpz += dj02 * cam.fx * (xt / z) / (z * z);
+      dpz += dj02 * cfx * (xt / z) / (z * z);
     }
     if (cy_free) {
-      dpy += -dj12 * cam.fy / (z * z);
-      dpz += dj12 * 2.0 * cam.fy * py / (z * z * z);
+      dpy += -dj12 * cfy / (z * z);
+      dpz += dj12 * 2.0f * cfy * py / (z * z * z);
     } else {
-      dpz += dj12 * cam.fy * (yt / z) / (z * z);
+      dpz += dj12 * cfy * (yt / z) / (z * z);
     }
     // projected centre
-    dpx += gx * cam.fx / z;
-    dpy += gy * cam.fy / z;
-    dpz += -gx * cam.fx * px / (z * z) - gy * cam.fy * py / (z * z);
+    dpx += gx * cfx / z;
+    dpy += gy * cfy / z;
+    dpz += -gx * cfx * px / (z * z) - gy * cfy * py / (z * z);
     // p = W mean + t
     dm[0] += W[0] * dpx + W[3] * dpy + W[6] * dpz;
     dm[1] += W[1] * dpx + W[4] * dpy + W[7] * dpz;
     dm[2] += W[2] * dpx + W[5] * dpy + W[8] * dpz;
     // Sigma = M M^T: dM = 2 dS M; M = R diag(s)
-    double dR[3][3];
+    real dR[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        const double dMij = 2.0 * (dS[i][0] * M[0][j] + dS[i][1] * M[1][j] + dS[i][2] * M[2][j]);
+        const real dMij = 2.0f * (dS[i][0] * M[0][j] + dS[i][1] * M[1][j] + dS[i][2] * M[2][j]);
         dR[i][j] = dMij * sc[j];
         dls[j] += dMij * R[i][j] * sc[j];
       }
     // R(q_hat), q_hat = q / |q|
-    const double dw = 2 * (-qz * dR[0][1] + qy * dR[0][2] + qz * dR[1][0] - qx * dR[1][2] - qy * dR[2][0] + qx * dR[2][1]);
-    const double dx_ = 2 * (qy * dR[0][1] + qz * dR[0][2] + qy * dR[1][0] - 2 * qx * dR[1][1] - qw * dR[1][2] +
+    const real dw = 2 * (-qz * dR[0][1] + qy * dR[0][2] + qz * dR[1][0] - qx * dR[1][2] - qy * dR[2][0] + qx * dR[2][1]);
+    const real dx_ = 2 * (qy * dR[0][1] + qz * dR[0][2] + qy * dR[1][0] - 2 * qx * dR[1][1] - qw * dR[1][2] +
                             qz * dR[2][0] + qw * dR[2][1] - 2 * qx * dR[2][2]);
-    const double dy_ = 2 * (-2 * qy * dR[0][0] + qx * dR[0][1] + qw * dR[0][2] + qx * dR[1][0] + qz * dR[1][2] -
+    const real dy_ = 2 * (-2 * qy * dR[0][0] + qx * dR[0][1] + qw * dR[0][2] + qx * dR[1][0] + qz * dR[1][2] -
                             qw * dR[2][0] + qz * dR[2][1] - 2 * qy * dR[2][2]);
-    const double dz_ = 2 * (-2 * qz * dR[0][0] - qw * dR[0][1] + qx * dR[0][2] + qw * dR[1][0] - 2 * qz * dR[1][1] +
+    const real dz_ = 2 * (-2 * qz * dR[0][0] - qw * dR[0][1] + qx * dR[0][2] + qw * dR[1][0] - 2 * qz * dR[1][1] +
                             qy * dR[1][2] + qx * dR[2][0] + qy * dR[2][1]);
-    const double dotq = dw * qw + dx_ * qx + dy_ * qy + dz_ * qz;
+    const real dotq = dw * qw + dx_ * qx + dy_ * qy + dz_ * qz;
     dq[0] = (dw - dotq * qw) * qn;
     dq[1] = (dx_ - dotq * qx) * qn;
     dq[2] = (dy_ - dotq * qy) * qn;
     dq[3] = (dz_ - dotq * qz) * qn;
-  } else if (d_sh) {
-    for (int i = 0; i < 3 * K; ++i) d_sh[g * 3 * K + i] = 0.f;
   }
   if (d_means)
     for (int i = 0; i < 3; ++i) d_means[3 * g + i] = (float)dm[i];
@@ -625,6 +691,10 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
   if (d_quats)
     for (int i = 0; i < 4; ++i) d_quats[4 * g + i] = (float)dq[i];
   if (d_logits) d_logits[g] = (float)dlogit;
+  }  // g < n
+  __syncthreads();
+  if (d_sh)
+    for (int64_t i = threadIdx.x; i < n_here * 3 * K; i += blockDim.x) d_sh[g0 * 3 * K + i] = sh_out[i];
 }
 
 int64_t preprocess_blocks(int64_t n) { return (n + 255) / 256; }
@@ -648,9 +718,13 @@ hipError_t launch_preprocess_backward(const DeviceScene& s, const CamArgs& cam, 
                                       const adr_scene_grads& out, hipStream_t stream) {
   if (s.n == 0) return hipSuccess;
   static const ShConsts shc = make_sh_consts();
-  preprocess_backward_kernel<<<dim3((unsigned)preprocess_blocks(s.n)), 256, 0, stream>>>(
-      s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc, cam, lowpass, grad2d, out.d_means, out.d_log_scales,
-      out.d_quats, out.d_opacity_logits, out.d_sh);
+  auto* kernel = s.n_coeff == 1   ? preprocess_backward_kernel<1>
+                 : s.n_coeff == 4 ? preprocess_backward_kernel<4>
+                 : s.n_coeff == 9 ? preprocess_backward_kernel<9>
+                                  : preprocess_backward_kernel<16>;
+  kernel<<<dim3((unsigned)preprocess_blocks(s.n)), 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, shc, cam,
+                                                                      lowpass, grad2d, out.d_means, out.d_log_scales,
+                                                                      out.d_quats, out.d_opacity_logits, out.d_sh);
   return hipGetLastError();
 }
 

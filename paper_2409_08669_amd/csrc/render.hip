@@ -707,13 +707,21 @@ __global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __rest
 // Each pixel walks its tile list back to front from the last entry it
 // examined (l_iter of the forward), recovering T_k = T_{k+1} / (1 - alpha_k)
 // from the final transmittance, so no per-entry state is stored. Which entries
-// it blended is decided exactly as in the forward (the FP32 exponent outside
-// the Gaussian's error band, FP64 inside it). Per list entry the wave adds up
-// its pixels' contributions and one lane adds them to the Gaussian's nine
-// screen-space gradients.
-__device__ __forceinline__ float wave_sum_f32(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+// it blended is decided exactly as in the forward: the same staged values, the
+// FP32 exponent outside the Gaussian's error band and FP64 inside it. Per
+// batch of 64 list entries a wave stages the entries that meet its quadrant
+// and steps through them from the last to the first, all lanes on the same
+// entry; a step where some pixel blends sums the nine contributions over
+// each 16-lane row with cross-lane (DPP) adds, and the first lane of each row
+// adds the row sums to the entry's LDS accumulators. After the batch one
+// global add per entry and component goes to the Gaussian's screen-space
+// gradients.
+// Sum over each 16-lane row of the wave (every lane of a row receives it).
+__device__ __forceinline__ float row_sum_dpp(float v) {
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0xb1, 0xf, 0xf, false);   // quad_perm 1,0,3,2
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x4e, 0xf, 0xf, false);   // quad_perm 2,3,0,1
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x141, 0xf, 0xf, false);  // row_half_mirror: 8 lanes
+  v += __builtin_amdgcn_update_dpp(0.f, v, 0x140, 0xf, 0xf, false);  // row_mirror: the 16-lane row
   return v;
 }
 
@@ -725,6 +733,7 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
   __shared__ Staged stage[4][64];
   __shared__ float4 stage_col[4][64];  // r, g, b, opacity
   __shared__ float4 stage_con[4][64];  // conic A, B, C, Gaussian id (bits)
+  __shared__ float acc[4][9][64];
   const int tile = blockIdx.x;
   const int W = cam.width, H = cam.height;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
@@ -735,6 +744,9 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
   const uint32_t e = min(ranges[2 * tile + 1], n_pairs);
   const uint32_t s = min(ranges[2 * tile], e);
   if (e <= s) return;
+  float* my_acc = &acc[wid][0][0];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) my_acc[c * 64 + lane] = 0.f;
   const int sb = lane >> 4;
   const int lx = (sb & 1) * kSub + (lane & 3), ly = (sb >> 1) * kSub + ((lane >> 2) & 3);
   const int pi = qx0 + lx, pj = qy0 + ly;
@@ -760,7 +772,7 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
     const uint32_t g = valid ? min(vals[k_lane], n_gauss - 1) : 0u;
     const SubMasks hm = sub_masks(valid ? load_box(rec, g) : kNoBox, qx0, qy0);
     const uint64_t any = hm.m[0] | hm.m[1] | hm.m[2] | hm.m[3];
-    if ((any >> lane) & 1ull) {
+    if ((any >> lane) & 1ull) {  // the forward's staging, bit for bit
       const RenderRecord& r = rec[g];
       Staged st;
       st.a = make_float4((float)(r.x - (double)qx0), (float)(r.y - (double)qy0), r.rc, r.rs);
@@ -773,22 +785,26 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint64_t my_mask = sb == 0 ? hm.m[0] : sb == 1 ? hm.m[1] : sb == 2 ? hm.m[2] : hm.m[3];
+    // the entries of this batch this lane examined and whose box meets its sub-block
+    uint64_t my_mask = sb == 0 ? hm.m[0] : sb == 1 ? hm.m[1] : sb == 2 ? hm.m[2] : hm.m[3];
+    const uint32_t lim = n_ex > base - s ? n_ex - (base - s) : 0u;
+    if (!inside || lim == 0) my_mask = 0ull;
+    if (lim < 64) my_mask &= (1ull << lim) - 1ull;
     uint64_t rem = any;
     while (rem) {
-      const int k = 63 - (int)__builtin_clzll(rem);  // back to front
+      const int k = 63 - (int)__builtin_clzll(rem);  // back to front, the whole wave on entry k
       rem &= ~(1ull << k);
-      const bool act = inside && ((my_mask >> k) & 1ull) && (base + (uint32_t)k < s + n_ex);
+      const bool act = (my_mask >> k) & 1ull;
       const float4 A = stage[wid][k].a, B = stage[wid][k].b;
       const float q = quad_form(A, B, fx, fy);
       bool blend = act && q >= bl.q_low;
       const bool near_low = act && fabsf(q - bl.q_low) < B.w;
       if (__ballot(near_low) != 0ull) {
-        if (near_low) {
-          const uint32_t gk = __float_as_uint(stage_con[wid][k].w);
-          blend = alpha_fp64_at(rec, exact, gk, pi, pj, bl.alpha_max_d) >= bl.alpha_low_d;
-        }
+        if (near_low)
+          blend = alpha_fp64_at(rec, exact, __float_as_uint(stage_con[wid][k].w), pi, pj, bl.alpha_max_d) >=
+                  bl.alpha_low_d;
       }
+      if (__ballot(blend) == 0ull) continue;
       float d[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (blend) {
         const float4 col = stage_col[wid][k], con = stage_con[wid][k];
@@ -797,7 +813,7 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
         const float G = __expf(power);
         const float a_raw = col.w * G;
         const float a = fminf(a_raw, bl.alpha_max);
-        const float inv = 1.f / (1.f - a);
+        const float inv = __builtin_amdgcn_rcpf(1.f - a);
         const float Tk = T * inv;
         const float dl_da = (g0 * col.x + g1 * col.y + g2 * col.z) * Tk - (g0 * S0 + g1 * S1 + g2 * S2 + bg_t) * inv;
         const float w = a * Tk;
@@ -818,12 +834,26 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
           d[5] = dl_da * G;
         }
       }
-      if (__ballot(blend) != 0ull) {
-        const uint32_t gk = __float_as_uint(stage_con[wid][k].w);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const float v = wave_sum_f32(d[i]);
-          if (lane == 0 && v != 0.f) atomicAdd(&grad2d[(int64_t)gk * kGrad2d + i], v);
+      for (int c = 0; c < 9; ++c) d[c] = row_sum_dpp(d[c]);
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c)
+          if (d[c] != 0.f) atomicAdd(&my_acc[c * 64 + k], d[c]);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // lane k adds entry k's sums to its Gaussian and clears them
+    if ((any >> lane) & 1ull) {
+      const uint32_t gk = __float_as_uint(stage_con[wid][lane].w);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        const float v = my_acc[c * 64 + lane];
+        if (v != 0.f) {
+          atomicAdd(&grad2d[(int64_t)gk * kGrad2d + c], v);
+          my_acc[c * 64 + lane] = 0.f;
         }
       }
     }
