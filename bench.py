@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--cpu-tiles", type=int, default=2048)
-    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only"], default=None,
+    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward"], default=None,
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
                     help="skip the alpha_low sweep (frames/s and PSNR at 1, 2, 4, 8 / 255)")
@@ -160,7 +160,9 @@ def main():
     # AABB pair culling alone, without reusing the extent inside Render.
     modes = {"3sigma": (P.ADR_CULL_3SIGMA, 0), "adaptive": (P.ADR_CULL_ADAPTIVE, 0),
              "aabb": (P.ADR_CULL_AABB, 0), "aabb_pairs_only": (P.ADR_CULL_AABB, P.ADR_FLAG_NO_QUAD_CULL)}
-    if args.only:
+    if args.only == "backward":
+        modes = {}  # the backward section below runs on its own
+    elif args.only:
         modes = {args.only: modes[args.only]}
     results = {}
     images = {}
@@ -213,8 +215,10 @@ def main():
             results[name]["load_imbalance_E_exec_over_E_alg"] = round(float(64 * wave_max.sum() / max(li.sum(), 1)), 4)
         log(f"mode {name}: {results[name]['fps']:.1f} frames/s, pairs {n_pairs}, stages "
             + ", ".join(f"{k} {v:.3f}" for k, v in results[name]["stages_ms"].items()))
-    first = next(iter(images.values()))
-    identical = all(bool(torch.equal(first, im)) for im in images.values())
+    identical = True
+    if images:
+        first = next(iter(images.values()))
+        identical = all(bool(torch.equal(first, im)) for im in images.values())
     if args.copy_probe_mib:
         n_el = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n_el, device=dev)
@@ -264,7 +268,7 @@ def main():
     # seeded dL/dimage, timed alone (the same forward differentiated again)
     # and as forward + backward back to back.
     backward = None
-    if not args.only and not args.no_backward:
+    if (not args.only or args.only == "backward") and not args.no_backward:
         params = P.RenderParams(cull=P.ADR_CULL_AABB)
         frame = {k: out[k] for k in ("image", "final_t", "l_iter")}
         gen = torch.Generator(device=dev).manual_seed(args.seed)
@@ -289,6 +293,9 @@ def main():
                     "frames_per_s_forward_plus_backward": round(1.0 / fwd_bwd, 2),
                     "grad_abs_max": {k: float(v.abs().max()) for k, v in g.items()}}
         log(f"backward: {bwd * 1e3:.3f} ms alone, forward + backward {fwd_bwd * 1e3:.3f} ms")
+    if args.only == "backward":
+        print(json.dumps({"mode": "backward", "backward": backward}), flush=True)
+        return
     if args.only:
         r = results[args.only]
         print(json.dumps({"mode": args.only, "fps": round(r["fps"], 2), "pairs": r["pairs"],
