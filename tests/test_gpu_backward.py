@@ -130,3 +130,17 @@ def test_backward_needs_the_matching_forward(P):
         P.render_backward(scene, cam, P.RenderParams(cull=0), ws, frame, dl)
     P.render_backward(scene, cam, P.RenderParams(), ws, frame, dl)
     torch.cuda.synchronize()
+
+
+def test_gaussians_behind_the_camera_get_zero_gradients(P):
+    """Every Gaussian behind the near plane: the frame is the background and
+    every gradient element is written as zero."""
+    import torch
+    s = f32(scene_small_sh3(100, seed=14))
+    s.means[:, 2] = -6.0  # camera at z = -4 looking along +z
+    cam = camera_small(32, 32)
+    prm = P.RenderParams(cull=2, background=(0.3, 0.2, 0.1))
+    g, img = gpu_grads(P, s, cam, prm, np.ones((3, 32, 32)))
+    for k in KEYS:
+        assert not np.any(g[k]), k
+    assert np.allclose(img, np.array([0.3, 0.2, 0.1])[:, None, None])
