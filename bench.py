@@ -52,7 +52,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--cpu-tiles", type=int, default=2048)
-    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward"], default=None,
+    ap.add_argument("--train-iters", type=int, default=600, help="iterations per run of --only train")
+    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train"],
+                    default=None,
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
                     help="skip the alpha_low sweep (frames/s and PSNR at 1, 2, 4, 8 / 255)")
@@ -129,6 +131,13 @@ def measured_traffic(kernel):
 
 def main():
     args = parse()
+    if args.only == "train":
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"  # torch takes the device first
+        import paper_2409_08669_amd as P
+        P.load()
+        print(json.dumps({"mode": "train", "train": train_load_balancing(P, args)}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (a multi-GPU split is "
                                    "described, not implemented)", "n_gpus": args.gpus}))
@@ -379,6 +388,117 @@ def main():
         "paper_context": "paper reports ~3.1x over 3DGS (Ours-Full, RTX 3090, trained scenes); AABB alone 1.65-2.11x",
     }
     print(json.dumps(line), flush=True)
+
+
+def _ssim(img, ref):
+    """Mean SSIM of two (3, H, W) images: 11 x 11 Gaussian window, sigma 1.5,
+    C1 = 0.01^2, C2 = 0.03^2 (the usual constants for [0, 1] images)."""
+    import torch
+    import torch.nn.functional as F
+    x = torch.arange(11, dtype=img.dtype, device=img.device) - 5.0
+    g = torch.exp(-x * x / (2 * 1.5 ** 2))
+    g = g / g.sum()
+    win = (g[:, None] * g[None, :]).expand(3, 1, 11, 11).contiguous()
+    a, b = img[None], ref[None]
+    mu_a = F.conv2d(a, win, padding=5, groups=3)
+    mu_b = F.conv2d(b, win, padding=5, groups=3)
+    s_aa = F.conv2d(a * a, win, padding=5, groups=3) - mu_a * mu_a
+    s_bb = F.conv2d(b * b, win, padding=5, groups=3) - mu_b * mu_b
+    s_ab = F.conv2d(a * b, win, padding=5, groups=3) - mu_a * mu_b
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    m = ((2 * mu_a * mu_b + c1) * (2 * s_ab + c2)) / ((mu_a * mu_a + mu_b * mu_b + c1) * (s_aa + s_bb + c2))
+    return m.mean()
+
+
+def train_load_balancing(P, args):
+    """The load-balancing loss as training (Eqs. 12-14): starting from a
+    synthetic scene, fit its own renders from 16 orbit views with
+    L = l1 L1 + ls (1 - SSIM) + ll std(l_blend) for ll = 0.45 (the paper's
+    weight), 0.1, 0.02 and 0 (control), (l1, ls) = (0.8, 0.2) (1 - ll) (the
+    3DGS split of what the load weight leaves). The load's gradient reaches the Gaussians through
+    adr_render_backward_load (slope 1 per blended alpha). Adam with the 3DGS
+    learning rates. Reports, per run, PSNR against the targets, the std of the
+    per-pixel load and frames/s over the views, before and after."""
+    import numpy as np
+    import torch
+    from synth import scene_clusters, camera_orbit
+    torch.manual_seed(args.seed)
+    n, w, h, views = 200_000, 480, 272, 16
+    gt = scene_clusters(n, seed=args.seed + 7, sh_degree=0)
+    cams = [camera_orbit(30.0, 20.0, 360.0 * k / views, w, h, 60.0) for k in range(views)]
+    prm = P.RenderParams(cull=P.ADR_CULL_AABB)
+    ws = P.Workspace()
+    dev = "cuda"
+
+    def frame():
+        return dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
+                    l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
+                    l_blend=torch.empty((h, w), dtype=torch.int32, device=dev))
+
+    def evaluate(scene, targets=None):
+        imgs, stds = [], []
+        for cam in cams:
+            f = frame()
+            P.render(scene, cam, prm, ws, **f)
+            imgs.append(f["image"].clone())
+            stds.append(float(f["l_blend"].float().std(unbiased=False)))
+        torch.cuda.synchronize()
+        for cam in cams:  # warm
+            P.render(scene, cam, prm, ws, **f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            for cam in cams:
+                P.render(scene, cam, prm, ws, **f)
+        torch.cuda.synchronize()
+        fps = 5 * len(cams) / (time.perf_counter() - t0)
+        psnr = None
+        if targets is not None:
+            mse = float(torch.stack([((a.clamp(0, 1) - b.clamp(0, 1)) ** 2).mean() for a, b in zip(imgs, targets)]).mean())
+            psnr = None if mse == 0.0 else 10.0 * math.log10(1.0 / mse)
+        return imgs, float(np.mean(stds)), fps, psnr
+
+    gt_scene = P.Scene.from_synth(gt)
+    targets, std_gt, fps_gt, _ = evaluate(gt_scene)
+    log(f"train: {n} Gaussians, {views} views at {w}x{h}; targets std(l_blend) {std_gt:.2f}, {fps_gt:.0f} frames/s")
+    runs = []
+    for ll in (0.45, 0.1, 0.02, 0.0):
+        l1, ls = 0.8 * (1.0 - ll), 0.2 * (1.0 - ll)  # the weights sum to 1 (Eq. 14)
+        t = {k: torch.tensor(np.asarray(getattr(gt, k), dtype=np.float32), device=dev)
+             for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+        lrs = {"means": 1.6e-4 * 10.0, "log_scales": 5e-3, "quats": 1e-3, "opacity_logits": 5e-2, "sh": 2.5e-3}
+        opt = torch.optim.Adam([{"params": [t[k]], "lr": lrs[k]} for k in t], eps=1e-15)
+        t0 = time.perf_counter()
+        for it in range(args.train_iters):
+            cam = cams[it % views]
+            scene = P.Scene(t["means"], t["log_scales"], t["quats"], t["opacity_logits"], t["sh"], 0)
+            f = frame()
+            P.render(scene, cam, prm, ws, **f)
+            img = f["image"].detach().requires_grad_(True)
+            loss_img = l1 * (img - targets[it % views]).abs().mean() + ls * (1.0 - _ssim(img, targets[it % views]))
+            loss_img.backward()
+            dload = None
+            if ll > 0:
+                lb = f["l_blend"].float()
+                sd = lb.std(unbiased=False)
+                if float(sd) > 0:
+                    dload = ll * (lb - lb.mean()) / (lb.numel() * sd)  # d std / d l_i, Eq. 13
+            g = P.render_backward(scene, cam, prm, ws, f, img.grad, dl_dload=dload)
+            for k in t:
+                t[k].grad = g[k]
+            opt.step()
+            opt.zero_grad(set_to_none=True)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        scene = P.Scene(t["means"], t["log_scales"], t["quats"], t["opacity_logits"], t["sh"], 0)
+        _, std_after, fps_after, psnr = evaluate(scene, targets)
+        runs.append({"lambda_l1": l1, "lambda_ssim": ls, "lambda_load": ll, "iters": args.train_iters,
+                     "train_s": round(secs, 2), "psnr_db_vs_targets": None if psnr is None else round(psnr, 3),
+                     "load_std_before": round(std_gt, 3), "load_std_after": round(std_after, 3),
+                     "fps_before": round(fps_gt, 1), "fps_after": round(fps_after, 1)})
+        log(f"train lambda_load {ll}: std(l_blend) {std_gt:.2f} -> {std_after:.2f}, "
+            f"{fps_gt:.0f} -> {fps_after:.0f} frames/s, PSNR {psnr}")
+    return {"gaussians": n, "views": views, "width": w, "height": h, "cull": "aabb", "runs": runs}
 
 
 def serve_benchmark(P, args):

@@ -184,6 +184,17 @@ adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, co
                                const adr_frame* fwd, const float* dl_dimage, adr_scene_grads* grads,
                                adr_workspace* ws, void* stream);
 
+/* adr_render_backward with a second term: dl_dload (H x W float32, device, may
+ * be NULL) is dL/dl_blend per pixel for a loss on the per-pixel load (Eq. 12;
+ * e.g. its standard deviation, Eq. 13, in the load-balancing loss, Eq. 14).
+ * The load is an integer count; its derivative is read as 1 with respect to
+ * the alpha of every entry the pixel blended (a straight-through reading; the
+ * paper does not say how the load's gradient is formed). Same requirements,
+ * errors and outputs as adr_render_backward. */
+adr_status adr_render_backward_load(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
+                                    const adr_frame* fwd, const float* dl_dimage, const float* dl_dload,
+                                    adr_scene_grads* grads, adr_workspace* ws, void* stream);
+
 /* Stage durations (ms) of the last adr_render on ws that had ADR_FLAG_TIMING:
  * [0] preprocess, [1] host wait for the pair count, [2] depth sort of the
  * Gaussians, [3] inclusive sum, [4] duplicate with keys, [5] tile sort of the

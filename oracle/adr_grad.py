@@ -118,8 +118,11 @@ def _preprocess(means, log_scales, quats, logits, sh, degree, cam, params: O.Par
     return x, y, conic, opacity, color
 
 
-def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None) -> dict:
-    """Gradient of L = sum(dl_dimage * image) with respect to the scene inputs.
+def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None, dl_dload=None) -> dict:
+    """Gradient of L = sum(dl_dimage * image) + sum(dl_dload * l_blend) with
+    respect to the scene inputs, where the per-pixel load l_blend (Eq. 12) is
+    taken through the surrogate sum of the blended alphas (slope 1 per blended
+    entry; the paper does not say how the integer load is differentiated).
 
     dl_dimage: (3, H, W). fwd: the forward oracle's render_frame result for the
     same inputs (computed here when absent); its sorted lists, tile ranges and
@@ -133,6 +136,7 @@ def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None
     x, y, conic, opacity, color = _preprocess(leaf["means"], leaf["log_scales"], leaf["quats"],
                                               leaf["opacity_logits"], leaf["sh"], scene.sh_degree, cam, params)
     w = torch.as_tensor(np.asarray(dl_dimage, dtype=np.float64))
+    wl = None if dl_dload is None else torch.as_tensor(np.asarray(dl_dload, dtype=np.float64))
     bg = torch.as_tensor(np.asarray(params.background, dtype=np.float64))
     values = np.asarray(fwd["values"], dtype=np.int64)
     ranges = np.asarray(fwd["ranges"], dtype=np.int64)
@@ -168,6 +172,8 @@ def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None
         t_fin = t_after[:, -1]
         out = c_pix + t_fin[:, None] * bg[None, :]
         loss = loss + (wt * out).sum()
+        if wl is not None:
+            loss = loss + (wl[jj, ii] * a.sum(dim=1)).sum()  # sum of blended alphas per pixel
     grads = torch.autograd.grad(loss, [leaf[k] for k in ("means", "log_scales", "quats", "opacity_logits", "sh")],
                                 allow_unused=True)
     res = {}
@@ -175,6 +181,30 @@ def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None
         res[k] = np.zeros(leaf[k].shape) if gval is None else gval.detach().numpy()
     res["loss"] = float(loss.detach())
     return res
+
+
+def blended_alpha_sum(scene, cam, params: O.Params) -> np.ndarray:
+    """Per-pixel sum of the alphas of the entries each pixel blends (the load
+    surrogate), from the forward oracle's decisions, in NumPy FP64."""
+    fr = O.render_frame(scene, cam, params)
+    pre = fr["pre"]
+    out = np.zeros((cam.height, cam.width))
+    tx_n, ty_n = O.n_tiles(cam)
+    for t in range(tx_n * ty_n):
+        s, e = int(fr["ranges"][t, 0]), int(fr["ranges"][t, 1])
+        if e <= s:
+            continue
+        tx, ty = t % tx_n, t // tx_n
+        for j in range(ty * O.TILE, min((ty + 1) * O.TILE, cam.height)):
+            for i in range(tx * O.TILE, min((tx + 1) * O.TILE, cam.width)):
+                n_ex = int(fr["l_iter"][j, i])
+                g = np.asarray(fr["values"][s:s + n_ex], dtype=np.int64)
+                dx, dy = pre["x"][g] - i, pre["y"][g] - j
+                con = pre["conic"][g]
+                power = -0.5 * (con[:, 0] * dx * dx + 2.0 * con[:, 1] * dx * dy + con[:, 2] * dy * dy)
+                a = np.minimum(params.alpha_max, pre["opacity"][g] * np.exp(power))
+                out[j, i] = float(a[a >= params.alpha_low].sum())
+    return out
 
 
 def loss_of(scene, cam, params: O.Params, dl_dimage) -> float:

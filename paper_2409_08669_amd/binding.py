@@ -36,7 +36,7 @@ STAGES = ("preprocess", "host_wait", "depth_sort", "inclusive_sum", "duplicate",
 
 EXPORTS = (
     "adr_create_scene", "adr_destroy_scene", "adr_scene_size", "adr_scene_bytes",
-    "adr_workspace_create", "adr_workspace_destroy", "adr_render", "adr_render_backward",
+    "adr_workspace_create", "adr_workspace_destroy", "adr_render", "adr_render_backward", "adr_render_backward_load",
     "adr_workspace_stage_times", "adr_workspace_counters", "adr_last_error", "adr_version",
     "adr_server_create", "adr_server_destroy", "adr_server_submit", "adr_server_wait", "adr_clock_s",
 )
@@ -110,6 +110,10 @@ def load(path=None):
     lib.adr_render_backward.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
                                         ctypes.POINTER(adr_frame), vp, ctypes.POINTER(adr_scene_grads), vp, vp]
     lib.adr_render_backward.restype = i32
+    lib.adr_render_backward_load.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
+                                             ctypes.POINTER(adr_frame), vp, vp, ctypes.POINTER(adr_scene_grads), vp,
+                                             vp]
+    lib.adr_render_backward_load.restype = i32
     lib.adr_workspace_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.adr_workspace_stage_times.restype = i32
     lib.adr_workspace_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
@@ -341,13 +345,15 @@ def render_frame(scene: Scene, cam, params: RenderParams, ws: Workspace = None, 
 
 
 def render_backward(scene: Scene, cam, params: RenderParams, ws: Workspace, frame: dict, dl_dimage,
-                    stream=None) -> dict:
+                    stream=None, dl_dload=None) -> dict:
     """adr_render_backward: gradients of L = sum(dl_dimage * image) with
     respect to the scene inputs, for the frame that the last render() on ws
     drew from the same scene, camera and params (frame: its outputs; final_t
     and l_iter are required). Returns float32 device tensors shaped like the
     scene arrays: means (N, 3), log_scales (N, 3), quats (N, 4),
-    opacity_logits (N,), sh (N, K, 3)."""
+    opacity_logits (N,), sh (N, K, 3). dl_dload (H, W), optional: dL/d(per-pixel
+    load l_blend), taken through the alpha of every blended entry with slope 1
+    (adr_render_backward_load)."""
     import torch
 
     lib = load()
@@ -366,9 +372,15 @@ def render_backward(scene: Scene, cam, params: RenderParams, ws: Workspace, fram
     p = params.to_c()
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
-    _check(lib.adr_render_backward(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
-                                   ctypes.c_void_p(dl.data_ptr()), ctypes.byref(g), ws.handle,
-                                   ctypes.c_void_p(int(stream))))
+    if dl_dload is None:
+        _check(lib.adr_render_backward(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
+                                       ctypes.c_void_p(dl.data_ptr()), ctypes.byref(g), ws.handle,
+                                       ctypes.c_void_p(int(stream))))
+    else:
+        dload = dl_dload.contiguous().float()
+        _check(lib.adr_render_backward_load(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
+                                            ctypes.c_void_p(dl.data_ptr()), ctypes.c_void_p(dload.data_ptr()),
+                                            ctypes.byref(g), ws.handle, ctypes.c_void_p(int(stream))))
     return grads
 
 

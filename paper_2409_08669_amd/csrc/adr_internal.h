@@ -222,7 +222,8 @@ constexpr int kGrad2d = 10;
 hipError_t launch_render_backward(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
                                   const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
                                   const BlendArgs& blend, const float* final_t, const uint32_t* l_iter,
-                                  const float* dl_dimage, float* grad2d, hipStream_t stream);
+                                  const float* dl_dimage, const float* dl_dload, float* grad2d,
+                                  hipStream_t stream);
 hipError_t launch_preprocess_backward(const DeviceScene& s, const CamArgs& cam, double lowpass, const float* grad2d,
                                       const adr_scene_grads& out, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t stream);

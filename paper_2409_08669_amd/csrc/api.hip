@@ -432,9 +432,10 @@ bool same_params(const adr_render_params& a, const adr_render_params& b) {
 
 }  // namespace
 
-extern "C" adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
-                                          const adr_frame* fwd, const float* dl_dimage, adr_scene_grads* grads,
-                                          adr_workspace* ws, void* stream_ptr) {
+extern "C" adr_status adr_render_backward_load(const adr_scene* scene, const adr_camera* cam,
+                                               const adr_render_params* p, const adr_frame* fwd,
+                                               const float* dl_dimage, const float* dl_dload,
+                                               adr_scene_grads* grads, adr_workspace* ws, void* stream_ptr) {
   adr_status st = validate(scene, cam, p, fwd, ws);
   if (st != ADR_OK) return st;
   if (!dl_dimage || !grads || !fwd->final_t || !fwd->l_iter) {
@@ -455,9 +456,15 @@ extern "C" adr_status adr_render_backward(const adr_scene* scene, const adr_came
   CamArgs ca = camera_args(cam, p);
   BlendArgs bl = blend_args(p);
   ADR_HIP(launch_render_backward(ws->rec, ws->exact, ws->last_vals, ws->ranges, ws->last_pairs, s.n, ca, bl,
-                                 fwd->final_t, fwd->l_iter, dl_dimage, ws->grad2d, stream));
+                                 fwd->final_t, fwd->l_iter, dl_dimage, dl_dload, ws->grad2d, stream));
   ADR_HIP(launch_preprocess_backward(s, ca, p->lowpass, ws->grad2d, *grads, stream));
   return ADR_OK;
+}
+
+extern "C" adr_status adr_render_backward(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                          const adr_frame* fwd, const float* dl_dimage, adr_scene_grads* grads,
+                                          adr_workspace* ws, void* stream) {
+  return adr_render_backward_load(scene, cam, p, fwd, dl_dimage, nullptr, grads, ws, stream);
 }
 
 extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n) {

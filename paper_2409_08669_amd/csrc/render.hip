@@ -729,7 +729,7 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
     const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, uint32_t n_pairs, uint32_t n_gauss, CamArgs cam, BlendArgs bl,
     const float* __restrict__ final_t, const uint32_t* __restrict__ l_iter, const float* __restrict__ dl_dimage,
-    float* __restrict__ grad2d) {
+    const float* __restrict__ dl_dload, float* __restrict__ grad2d) {
   __shared__ Staged stage[4][64];
   __shared__ float4 stage_col[4][64];  // r, g, b, opacity
   __shared__ float4 stage_con[4][64];  // conic A, B, C, Gaussian id (bits)
@@ -759,6 +759,8 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
   const float g0 = inside ? dl_dimage[pix] : 0.f;
   const float g1 = inside ? dl_dimage[plane + pix] : 0.f;
   const float g2 = inside ? dl_dimage[2 * plane + pix] : 0.f;
+  // dL/d(load of this pixel): each blended entry counts 1, read as d load / d alpha = 1
+  const float g_load = (inside && dl_dload) ? dl_dload[pix] : 0.f;
   const float bg_t = T * (g0 * bl.bg[0] + g1 * bl.bg[1] + g2 * bl.bg[2]);
   float S0 = 0.f, S1 = 0.f, S2 = 0.f;
   uint32_t n_max = n_ex;
@@ -815,7 +817,8 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
         const float a = fminf(a_raw, bl.alpha_max);
         const float inv = __builtin_amdgcn_rcpf(1.f - a);
         const float Tk = T * inv;
-        const float dl_da = (g0 * col.x + g1 * col.y + g2 * col.z) * Tk - (g0 * S0 + g1 * S1 + g2 * S2 + bg_t) * inv;
+        const float dl_da =
+            (g0 * col.x + g1 * col.y + g2 * col.z) * Tk - (g0 * S0 + g1 * S1 + g2 * S2 + bg_t) * inv + g_load;
         const float w = a * Tk;
         d[6] = g0 * w;
         d[7] = g1 * w;
@@ -902,12 +905,13 @@ hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums,
 hipError_t launch_render_backward(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
                                   const uint32_t* ranges, int64_t n_pairs, int64_t n_gauss, const CamArgs& cam,
                                   const BlendArgs& blend, const float* final_t, const uint32_t* l_iter,
-                                  const float* dl_dimage, float* grad2d, hipStream_t stream) {
+                                  const float* dl_dimage, const float* dl_dload, float* grad2d,
+                                  hipStream_t stream) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   if (n_tiles <= 0 || n_pairs <= 0 || n_gauss <= 0) return hipSuccess;
   render_backward_kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(rec, exact, vals, ranges, (uint32_t)n_pairs,
                                                                       (uint32_t)n_gauss, cam, blend, final_t, l_iter,
-                                                                      dl_dimage, grad2d);
+                                                                      dl_dimage, dl_dload, grad2d);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ def f32(scene):
                  scene.sh_degree)
 
 
-def gpu_grads(P, scene, cam, params, w):
+def gpu_grads(P, scene, cam, params, w, wl=None):
     import torch
     sg = P.Scene.from_synth(scene)
     ws = P.Workspace()
@@ -47,7 +47,9 @@ def gpu_grads(P, scene, cam, params, w):
     frame = dict(image=torch.empty((3, h, wd), device="cuda"), final_t=torch.empty((h, wd), device="cuda"),
                  l_iter=torch.empty((h, wd), dtype=torch.int32, device="cuda"))
     P.render(sg, cam, params, ws, **frame)
-    g = P.render_backward(sg, cam, params, ws, frame, torch.as_tensor(w, dtype=torch.float32, device="cuda"))
+    dload = None if wl is None else torch.as_tensor(wl, dtype=torch.float32, device="cuda")
+    g = P.render_backward(sg, cam, params, ws, frame, torch.as_tensor(w, dtype=torch.float32, device="cuda"),
+                          dl_dload=dload)
     torch.cuda.synchronize()
     return {k: v.double().cpu().numpy() for k, v in g.items()}, frame["image"].cpu().numpy()
 
@@ -144,3 +146,18 @@ def test_gaussians_behind_the_camera_get_zero_gradients(P):
     for k in KEYS:
         assert not np.any(g[k]), k
     assert np.allclose(img, np.array([0.3, 0.2, 0.1])[:, None, None])
+
+
+@pytest.mark.parametrize("mode", [0, 2], ids=["3sigma", "aabb"])
+def test_load_term_gradients_match_the_oracle(P, mode):
+    """adr_render_backward_load: dL/d(per-pixel load) through the blended alphas
+    (slope 1), together with dL/dimage."""
+    scene = f32(scene_small_sh3(300, seed=15))
+    cam = camera_small(64, 48)
+    rng = np.random.default_rng(10)
+    w = rng.normal(size=(3, 48, 64))
+    wl = rng.normal(size=(48, 64))
+    say(f"load term, mode {mode}")
+    g, _ = gpu_grads(P, scene, cam, P.RenderParams(cull=mode), w, wl)
+    o = G.render_grad(scene, cam, O.Params(cull=mode), w, dl_dload=wl)
+    compare(g, o, f"load mode {mode}")

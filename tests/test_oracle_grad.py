@@ -91,3 +91,32 @@ def test_gaussians_behind_the_camera_get_no_gradient():
     for k in KEYS:
         assert not np.any(g[k][behind]), k
     assert np.any(g["means"])
+
+
+def test_load_surrogate_gradient_matches_central_differences():
+    """The load term: L = sum(w * image) + sum(wl * A) with A the per-pixel
+    sum of the blended alphas (computed here by a NumPy loop over pixels)."""
+    scene = sh3_scene(30, seed=8)
+    cam = camera_small(32, 24)
+    prm = O.Params(cull=O.CULL_AABB)
+    rng = np.random.default_rng(4)
+    w = rng.normal(size=(3, cam.height, cam.width))
+    wl = rng.normal(size=(cam.height, cam.width))
+    fwd = O.render_frame(scene, cam, prm)
+    assert fwd["alpha_margin"].min() > 1e-5 and fwd["t_margin"].min() > 1e-5
+    g = G.render_grad(scene, cam, prm, w, fwd, dl_dload=wl)
+
+    def total(sc):
+        return G.loss_of(sc, cam, prm, w) + float(np.sum(wl * G.blended_alpha_sum(sc, cam, prm)))
+
+    assert abs(g["loss"] - total(scene)) < 1e-11 * max(1.0, abs(g["loss"]))
+    hit = np.unique(np.asarray(fwd["values"], dtype=np.int64))
+    for key in ("means", "log_scales", "quats", "opacity_logits"):
+        arr = np.asarray(getattr(scene, key))
+        for _ in range(4):
+            gi = int(rng.choice(hit))
+            idx = (gi,) + tuple(int(rng.integers(0, d)) for d in arr.shape[1:])
+            h = 1e-7 * max(1.0, abs(float(arr[idx])))
+            fd = (total(perturbed(scene, key, idx, h)) - total(perturbed(scene, key, idx, -h))) / (2 * h)
+            an = float(g[key][idx])
+            assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (key, idx, fd, an)
