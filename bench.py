@@ -58,8 +58,9 @@ def parse():
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
                     help="skip the alpha_low sweep (frames/s and PSNR at 1, 2, 4, 8 / 255)")
-    ap.add_argument("--no-backward", action="store_true",
-                    help="skip the gradient timing (adr_render_backward on the AABB frame)")
+    ap.add_argument("--backward", action="store_true",
+                    help="also time the gradients (adr_render_backward on the AABB frame) after the modes; "
+                         "off by default, --only backward times them alone")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (scales HBM counters)")
     return ap.parse_args()
@@ -277,7 +278,7 @@ def main():
     # seeded dL/dimage, timed alone (the same forward differentiated again)
     # and as forward + backward back to back.
     backward = None
-    if (not args.only or args.only == "backward") and not args.no_backward:
+    if (not args.only and args.backward) or args.only == "backward":
         params = P.RenderParams(cull=P.ADR_CULL_AABB)
         frame = {k: out[k] for k in ("image", "final_t", "l_iter")}
         gen = torch.Generator(device=dev).manual_seed(args.seed)

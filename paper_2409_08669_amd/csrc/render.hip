@@ -321,8 +321,9 @@ struct Pixel {
 // as 2^-23 T', which also covers the product terms of errors left out). When
 // T lands within 1.5 D (plus t_min's rounding) of t_min, the whole wave
 // recomputes the pixel's transmittance in FP64 over the list so far, and that
-// value decides the stop. A lane that has stopped evaluates only records with
-// exponent -1e30, which change nothing. Every lane of the wave must call it.
+// value decides the stop. A lane that has stopped evaluates only the null
+// record (exponent -1e30, band 0), which changes nothing. Every lane of the
+// wave must call it.
 template <bool kCap>
 __device__ __forceinline__ uint64_t blend_step(Pixel& px, const float4& A, const float4& B, const float4& col,
                                                int slot, uint32_t base, const uint32_t* gids, float fx, float fy,
@@ -574,7 +575,9 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
     // is list (depth) order, with the exact decision logic; two register
     // sets alternate as above. The wave steps while any lane has candidates
     // left. A lane that stops drops its remaining ones and turns the record
-    // already read for its next step into a no-op (exponent -1e30).
+    // already read for its next step into the null record (exponent -1e30 and
+    // band 0: a Gaussian decided in FP64 only has an infinite band, which
+    // would otherwise send the no-op step down the FP64 path).
     {
       uint64_t cm = done ? 0ull : cand;
       int s0 = next_slot(cm), s1 = next_slot(cm);
@@ -601,7 +604,7 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
             cm = 0;
             s0 = 64;
             s1 = 64;
-            B1.z = -1e30f;
+            B1 = make_float4(0.f, 0.f, -1e30f, 0.f);  // the null record: band 0 too, so no FP64 path is taken
           }
         }
         if (__ballot(s1 != 64) == 0) break;
@@ -623,7 +626,7 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
             cm = 0;
             s0 = 64;
             s1 = 64;
-            B0.z = -1e30f;
+            B0 = make_float4(0.f, 0.f, -1e30f, 0.f);
           }
         }
       }

@@ -138,6 +138,24 @@ def test_needle_scene_parity(P, ws, mode):
     check_load_sums(g, o)
 
 
+@pytest.mark.parametrize("n_weak", [0, 1])
+@pytest.mark.parametrize("mode", [0, 2], ids=["3sigma", "aabb"])
+def test_stopped_pixels_blend_nothing_more(P, ws, mode, n_weak):
+    """Pixels that stop at a wall while their quadrant goes on, with a
+    Gaussian decided in FP64 only right after the stop and a Gaussian 0 that
+    reaches them (tests/stop_scene.py): their colour, transmittance and
+    counters end at the stop, with the stop on either of the blend loop's two
+    alternating steps (n_weak 0 and 1)."""
+    from tests.stop_scene import stop_scene
+    s, cam, _ = stop_scene(n_weak)
+    say(f"stopped-pixel scene, {n_weak} weak walls, mode {mode}")
+    g = gpu_frame(P, ws, P.Scene.from_synth(s), cam, mode)
+    o = O.render_frame(s, cam, oracle_params(mode))
+    check_integer_stage(g, o, s.n)
+    check_pixels(g, o)
+    check_load_sums(g, o)
+
+
 def test_small_scene_modes_render_bitwise_identical(P, ws, small):
     _, sg, cam = small
     say("mode invariance, small scene")
