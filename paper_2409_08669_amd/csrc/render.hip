@@ -171,6 +171,12 @@ __device__ __forceinline__ uint2 load_box(const RenderRecord* __restrict__ rec, 
   return *reinterpret_cast<const uint2*>(&rec[g].box_x);
 }
 
+// The box of a list position past the list's end: lo 65535, hi 0 on both
+// axes. It meets no sub-block: a column test needs hi >= qx0, so qx0 = 0,
+// and there lo <= qx0 + 7 fails (a box with lo 1, hi 0 would pass both at
+// the image's first quadrant).
+__device__ __forceinline__ uint2 no_box() { return make_uint2(0xffffu, 0xffffu); }
+
 // Ballots of one batch: bit l of m[t] is set when the box of lane l's entry
 // meets sub-block t of the quadrant at (qx0, qy0).
 struct SubMasks {
@@ -470,7 +476,7 @@ __global__ void __launch_bounds__(256, 4) render_kernel(
   // before its use one iteration later: list positions past the end read the
   // last entry (their boxes are replaced by an empty one at use), and lanes
   // whose entry misses the quadrant read record 0 (one shared cache line).
-  const uint2 kNoBox = make_uint2(1u, 1u);  // lo 1 > hi 0: empty
+  const uint2 kNoBox = no_box();
   const uint32_t last = e > s ? e - 1 : s;  // the loop below runs only when e > s
   uint32_t g_b = 0, g_n1 = 0, raw_n2 = 0;
   uint2 box_n1 = kNoBox;
@@ -769,7 +775,7 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
   uint32_t n_max = n_ex;
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) n_max = max(n_max, (uint32_t)__shfl_xor((int)n_max, off, 64));
-  const uint2 kNoBox = make_uint2(1u, 1u);
+  const uint2 kNoBox = no_box();
   for (int b = ((int)n_max - 1) >> 6; b >= 0; --b) {
     const uint32_t base = s + 64u * (uint32_t)b;
     const uint32_t k_lane = base + (uint32_t)lane;

@@ -43,3 +43,21 @@ def test_stop_scene_preconditions(n_weak, mode):
     a0 = pre["opacity"][0] * np.exp(-0.5 * (c0[0] * dx * dx + 2 * c0[1] * dx * dy + c0[2] * dy * dy))
     assert (a0 >= prm.alpha_low).all()
     assert min(fr["t_margin"].min(), fr["alpha_margin"].min()) > 1e-6
+
+
+def test_empty_box_meets_no_sub_block():
+    """The blend kernels give list positions past a list's end the box
+    lo = 65535, hi = 0 on both axes (packed lo | hi << 16), and test a box
+    against the four 4 x 4 sub-blocks of the quadrant at (qx0, qy0) as
+    lo <= q0 + 3 + 4 c and hi >= q0 + 4 c per axis. Over every quadrant origin
+    an image of up to 65535 pixels has, that box meets none; the box
+    lo = 1, hi = 0 meets sub-block 0 of the first quadrant, which is what sent
+    the top-left pixels phantom copies of a tile's last entry."""
+    q0 = np.arange(0, 65536, 8, dtype=np.int64)
+
+    def meets(lo, hi):
+        return np.stack([(lo <= q0 + 3 + 4 * c) & (hi >= q0 + 4 * c) for c in (0, 1)])
+
+    assert not meets(0xffff, 0).any()
+    hit = meets(1, 0)
+    assert hit[0, 0] and hit.sum() == 1
