@@ -161,3 +161,23 @@ def test_load_term_gradients_match_the_oracle(P, mode):
     g, _ = gpu_grads(P, scene, cam, P.RenderParams(cull=mode), w, wl)
     o = G.render_grad(scene, cam, O.Params(cull=mode), w, dl_dload=wl)
     compare(g, o, f"load mode {mode}")
+
+
+@pytest.mark.parametrize("n_weak", [0, 1])
+@pytest.mark.parametrize("mode", [0, 2], ids=["3sigma", "aabb"])
+def test_gradients_on_the_stopped_pixel_scene(P, mode, n_weak):
+    """The hand-placed scene of tests/stop_scene.py: pixels of the image's
+    first quadrant stop at a wall with a Gaussian decided in FP64 only right
+    behind it, the rest of their wave goes on. The backward walk must take
+    the forward's decisions (stop, FP64-only blends) there too."""
+    from tests.stop_scene import stop_scene
+    scene, cam, _ = stop_scene(n_weak)
+    scene = f32(scene)
+    prm = O.Params(cull=mode)
+    w = np.random.default_rng(9).normal(size=(3, cam.height, cam.width))
+    say(f"stopped-pixel scene, {n_weak} weak walls, mode {mode}")
+    g, img = gpu_grads(P, scene, cam, P.RenderParams(cull=mode), w)
+    fwd = O.render_frame(scene, cam, prm)
+    assert np.abs(img - fwd["image"]).max() <= 2e-4
+    o = G.render_grad(scene, cam, prm, w, fwd)
+    compare(g, o, f"stop scene {n_weak} mode {mode}")
