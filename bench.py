@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--cpu-tiles", type=int, default=2048)
     ap.add_argument("--train-iters", type=int, default=600, help="iterations per run of --only train")
-    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train"],
+    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb"],
                     default=None,
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
@@ -132,6 +132,13 @@ def measured_traffic(kernel):
 
 def main():
     args = parse()
+    if args.only == "lb":
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        import paper_2409_08669_amd as P
+        P.load()
+        print(json.dumps({"mode": "lb", "lb": cap_sweep(P, args)}), flush=True)
+        return
     if args.only == "train":
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"  # torch takes the device first
@@ -409,6 +416,75 @@ def _ssim(img, ref):
     c1, c2 = 0.01 ** 2, 0.03 ** 2
     m = ((2 * mu_a * mu_b + c1) * (2 * s_ab + c2)) / ((mu_a * mu_a + mu_b * mu_b + c1) * (s_aa + s_bb + c2))
     return m.mean()
+
+
+def cap_sweep(P, args):
+    """The load-balancing mode (a render-time cap of K blends per pixel, the
+    reading of Sec. 4.4's compression of heavy-load pixels) on the
+    load-imbalanced workload: 3M Gaussians with 20% in 8 dense clusters,
+    1600x1040, the 32 poses of the orbit sweep. K = ceil(mean + kappa std) of
+    l_blend over the covered pixels of pose 0's exact AABB frame, kappa = 1, 2,
+    3. Per pose, exact AABB and each cap: frames/s (back-to-back frames),
+    std(l_blend) over all pixels (Eq. 13, from the exact integer sums), and the
+    PSNR of the capped image against the exact one (both clipped to [0, 1])."""
+    import numpy as np
+    import torch
+    from synth import scene_heavy, cameras_sweep
+
+    log("cap sweep: 3M-Gaussian load-imbalanced scene, 32 poses at 1600x1040")
+    sg = P.Scene.from_synth(scene_heavy(3_000_000, seed=args.seed))
+    cams = cameras_sweep(32)
+    ws = P.Workspace()
+    w, h = cams[0].width, cams[0].height
+    dev = "cuda"
+    out = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
+               l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
+               l_blend=torch.empty((h, w), dtype=torch.int32, device=dev),
+               load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
+    exact = P.RenderParams(cull=P.ADR_CULL_AABB)
+    P.render(sg, cams[0], exact, ws, **out)
+    lb = out["l_blend"][out["l_blend"] > 0].double()
+    lb_mean, lb_std = float(lb.mean()), float(lb.std(unbiased=False))
+    caps = {k: int(math.ceil(lb_mean + k * lb_std)) for k in (1, 2, 3)}
+    log(f"cap sweep: pose 0 covered-pixel l_blend mean {lb_mean:.2f} std {lb_std:.2f}, K {caps}")
+    n_rep = max(args.steps // 5, 3)
+
+    def run(cam, params):
+        for _ in range(2):
+            P.render(sg, cam, params, ws, **out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_rep):
+            P.render(sg, cam, params, ws, **out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n_rep
+        _, std_b = P.load_stats_from_sums(out["load_sums"].cpu().numpy()[0:2], w * h)
+        return 1.0 / dt, std_b, out["image"].clamp(0.0, 1.0).clone()
+
+    rows = []
+    for pi, cam in enumerate(cams):
+        fps_e, std_e, img_e = run(cam, exact)
+        row = {"pose": pi, "exact": {"fps": round(fps_e, 2), "std_blend": round(std_e, 3)}}
+        for k, cap in caps.items():
+            fps_c, std_c, img_c = run(cam, P.RenderParams(cull=P.ADR_CULL_AABB, lb_cap=cap))
+            mse = float(((img_c - img_e) ** 2).mean())
+            row[f"kappa{k}"] = {"fps": round(fps_c, 2), "std_blend": round(std_c, 3),
+                                "psnr_db": None if mse == 0.0 else round(10.0 * math.log10(1.0 / mse), 3)}
+        rows.append(row)
+        log(f"cap sweep pose {pi}: exact {fps_e:.1f} frames/s std {std_e:.2f}; "
+            + "; ".join(f"k{k} {row[f'kappa{k}']['fps']:.1f} fps std {row[f'kappa{k}']['std_blend']:.2f} "
+                        f"PSNR {row[f'kappa{k}']['psnr_db']}" for k in caps))
+    mean = {"exact": {"fps": round(float(np.mean([r["exact"]["fps"] for r in rows])), 2),
+                      "std_blend": round(float(np.mean([r["exact"]["std_blend"] for r in rows])), 3)}}
+    for k in caps:
+        ps = [r[f"kappa{k}"]["psnr_db"] for r in rows if r[f"kappa{k}"]["psnr_db"] is not None]
+        mean[f"kappa{k}"] = {"K": caps[k],
+                             "fps": round(float(np.mean([r[f"kappa{k}"]["fps"] for r in rows])), 2),
+                             "std_blend": round(float(np.mean([r[f"kappa{k}"]["std_blend"] for r in rows])), 3),
+                             "psnr_db": round(float(np.mean(ps)), 3) if ps else None}
+    return {"n_gaussians": 3_000_000, "width": w, "height": h, "poses": len(cams), "frames_per_setting": n_rep,
+            "pose0_covered_lblend_mean": round(lb_mean, 3), "pose0_covered_lblend_std": round(lb_std, 3),
+            "caps": caps, "mean": mean, "per_pose": rows}
 
 
 def train_load_balancing(P, args):
