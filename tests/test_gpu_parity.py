@@ -303,6 +303,39 @@ def test_headline_scale_integer_stage_and_sampled_tiles(P, ws):
 
 
 @pytest.mark.slow
+def test_4k_frame_integer_stage_and_sampled_tiles(P, ws):
+    """The largest frame size of the workloads: 1M Gaussians (SH3, seed 1),
+    3840x2160 from a 14 m orbit so that the scene reaches every image corner
+    (~9.8M pairs, 32400 tiles). AABB: the integer stage bit-exact, then the
+    image and counters on the four corner tiles, the 16 busiest and 32 seeded
+    tiles against the oracle; the 3-sigma image bitwise the AABB one."""
+    s = scene_clusters(1_000_000, seed=1)
+    cam = camera_orbit(14.0, 35.0, 200.0, 3840, 2160)
+    sg = P.Scene.from_synth(s)
+    pre = O.preprocess(s, cam, O.Params())
+    params = oracle_params(2)
+    rects = O.tile_rects(pre, cam, params)
+    keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+    ranges = O.tile_ranges(keys, cam)
+    say("1M G 3840x2160 AABB")
+    g = gpu_frame(P, ws, sg, cam, 2)
+    o = dict(tiles_touched=rects["tiles_touched"], n_pairs=int(keys.size), keys=keys, values=values, ranges=ranges)
+    check_integer_stage(g, o, s.n)
+    tx_n, ty_n = O.n_tiles(cam)
+    corners = np.array([0, tx_n - 1, (ty_n - 1) * tx_n, tx_n * ty_n - 1])
+    assert (ranges[corners, 1] > ranges[corners, 0]).all()  # the scene reaches every corner
+    busy = np.argsort(ranges[:, 1] - ranges[:, 0])[-16:]
+    rng = np.random.default_rng(13)
+    tiles = np.unique(np.concatenate([rng.choice(tx_n * ty_n, 32, replace=False), busy, corners]))
+    r = O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+    n_amb = check_pixels(g, r, mask=r["done"])
+    say(f"  pairs {g['n_pairs']}  sampled tiles {tiles.size}  ambiguous pixels {n_amb}")
+    b = gpu_frame(P, ws, sg, cam, 0, debug=False)
+    np.testing.assert_array_equal(b["image"], g["image"])
+    np.testing.assert_array_equal(b["l_blend"], g["l_blend"])
+
+
+@pytest.mark.slow
 def test_load_imbalanced_scene_exact_and_capped(P, ws):
     """3M Gaussians with 20% in 8 dense clusters, 1600x1040, first pose of the
     32-pose sweep (tile lists up to ~76k entries): the AABB integer stage
