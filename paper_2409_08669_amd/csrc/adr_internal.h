@@ -12,6 +12,7 @@
 namespace adr {
 
 constexpr int kTile = 16;     // 16 x 16 pixel tiles (Sec. 3.2)
+constexpr int kDupPairs = 2048;  // pairs emitted per DuplicateWithKeys workgroup
 constexpr int kQuad = 8;      // each wave of a tile's workgroup owns an 8 x 8 quadrant
 constexpr int kWave = 64;     // CDNA wavefront
 
@@ -120,6 +121,10 @@ struct adr_workspace {
   adr::SortBuffers depth;          // (depth key, id) of every Gaussian, sorted by depth
   uint32_t* scan_partials = nullptr;
   int64_t scan_partials_capacity = 0;
+  // per DuplicateWithKeys workgroup (kDupPairs pairs): the depth-order index
+  // of the Gaussian that holds its first pair, written by the InclusiveSum
+  uint32_t* dup_first = nullptr;
+  int64_t dup_first_capacity = 0;
   ulonglong4* block_parts = nullptr;  // per Preprocess workgroup: pairs, visible, depth-key min, max
   int64_t block_parts_capacity = 0;
   // per pair
@@ -194,11 +199,12 @@ int64_t preprocess_blocks(int64_t n);
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
                              hipStream_t stream);
 hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
-                                hipStream_t stream);
+                                uint32_t* dup_first, hipStream_t stream);
 int64_t inclusive_sum_partials(int64_t n);
-hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint2* tile_rect, int64_t n_vis,
-                            int64_t n_pairs, int32_t tiles_x, uint32_t* tile_keys, uint32_t* vals,
-                            hipStream_t stream);
+int64_t duplicate_blocks(int64_t n_pairs);
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* dup_first, const uint32_t* order,
+                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
+                            uint32_t* tile_keys, uint32_t* vals, hipStream_t stream);
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
                              uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
                              hipStream_t stream, const uint32_t* gather_src = nullptr,

@@ -83,6 +83,8 @@ adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
 adr_status ensure_pairs(adr_workspace* ws, int64_t p) {
   adr_status st;
   if ((st = ensure_sort_buffers(ws->pairs, p, "pair sort")) != ADR_OK) return st;
+  if ((st = grow(ws->dup_first, ws->dup_first_capacity, duplicate_blocks(p) + 1, "pair chunk starts")) != ADR_OK)
+    return st;
   return grow(ws->sort_scratch, ws->sort_scratch_capacity, sort_scratch_entries(p), "sort scratch");
 }
 
@@ -100,7 +102,7 @@ using namespace adr;
 static void free_workspace_buffers(adr_workspace* ws) {
   void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->touched_sorted, ws->depth.keys[0],
                   ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
-                  ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->sort_scratch, ws->ranges,
+                  ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->dup_first, ws->sort_scratch, ws->ranges,
                   ws->tile_order, ws->order_counts, ws->wave_sums, ws->dev_counters, ws->hists, ws->block_parts};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -361,10 +363,10 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   const uint32_t* order = ws->depth.vals[dsorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[3], stream));
   // Stage 2: InclusiveSum of tiles_touched over the Gaussians in depth order
-  ADR_HIP(launch_inclusive_sum(ws->touched_sorted, ws->offsets, n_vis, ws->scan_partials, stream));
+  ADR_HIP(launch_inclusive_sum(ws->touched_sorted, ws->offsets, n_vis, ws->scan_partials, ws->dup_first, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[4], stream));
   // Stage 3: DuplicateWithKeys, in depth order, keyed by tile id
-  ADR_HIP(launch_duplicate(ws->offsets, order, ws->tile_rect, n_vis, n_pairs, ca.tiles_x, ws->pairs.keys[0],
+  ADR_HIP(launch_duplicate(ws->offsets, ws->dup_first, order, ws->tile_rect, n_vis, n_pairs, ca.tiles_x, ws->pairs.keys[0],
                            ws->pairs.vals[0], stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[5], stream));
   // Stage 4b: stable sort by tile id; equal tiles keep the depth order

@@ -1,11 +1,10 @@
 // DuplicateWithKeys and IdentifyTileRanges (Sec. 3.2, stages 3 and 5).
 //
 // Pair emission is pair-parallel and balanced: workgroup b writes pairs
-// [2048 b, 2048 b + 2048). Two waves find the first and the last Gaussian
-// (in depth order) whose pairs fall in that range with a 64-way search of the
-// inclusive offsets (a handful of dependent loads instead of twenty), the
-// workgroup stages those Gaussians' offsets in LDS, and each pair finds its
-// Gaussian by binary search there. One Gaussian with a huge rectangle
+// [2048 b, 2048 b + 2048). The InclusiveSum has recorded, per such chunk, the
+// Gaussian (in depth order) holding its first pair; the workgroup stages the
+// offsets of the Gaussians from that one to the next chunk's in LDS, and each
+// pair finds its Gaussian by binary search there. One Gaussian with a huge rectangle
 // therefore spreads over many workgroups, and consecutive lanes write
 // consecutive pairs. Within a Gaussian the tiles are emitted row-major over
 // its tile rectangle. Each pair carries the tile id as its sort key; the depth
@@ -17,53 +16,25 @@ namespace adr {
 namespace {
 
 constexpr int kDupThreads = 256;
-constexpr int kDupPairs = 2048;  // pairs per workgroup
-
-// Smallest r in [0, n) with offsets[r] > p, for a non-decreasing array whose
-// last entry exceeds p; every lane of the wave returns it.
-__device__ uint32_t wave_search_gt(const uint32_t* __restrict__ offsets, uint32_t n, uint32_t p) {
-  const int lane = threadIdx.x & 63;
-  uint32_t lo = 0, hi = n;  // answer in [lo, hi)
-  while (hi - lo > 64) {
-    const uint32_t step = (hi - lo + 63) / 64;
-    const uint32_t at = lo + (uint32_t)lane * step;
-    const bool gt = at < hi ? offsets[at] > p : true;
-    const uint64_t m = __ballot(gt);  // the lanes from the first true one on
-    if (m == 0) {  // every sample (all below hi) is <= p: the answer lies past the last one
-      lo += 63u * step + 1u;
-      continue;
-    }
-    const int f = __ffsll((long long)m) - 1;
-    if (f == 0) return lo;
-    const uint32_t prev = lo + (uint32_t)(f - 1) * step;  // offsets[prev] <= p
-    const uint32_t cand = lo + (uint32_t)f * step;
-    lo = prev + 1;
-    hi = cand < hi ? cand + 1 : hi;
-  }
-  const uint32_t at = lo + (uint32_t)lane;
-  const bool gt = at < hi ? offsets[at] > p : true;
-  const uint64_t m = __ballot(gt);
-  return lo + (uint32_t)(__ffsll((long long)m) - 1);
-}
 
 __global__ void __launch_bounds__(kDupThreads) duplicate_kernel(const uint32_t* __restrict__ offsets,
+                                                                const uint32_t* __restrict__ dup_first,
                                                                 const uint32_t* __restrict__ order,
                                                                 const uint2* __restrict__ tile_rect, uint32_t n_vis,
                                                                 uint32_t n_pairs, int32_t tiles_x,
                                                                 uint32_t* __restrict__ tile_keys,
                                                                 uint32_t* __restrict__ vals) {
-  __shared__ uint32_t s_end[kDupPairs];  // inclusive offsets of the workgroup's Gaussians
-  __shared__ uint32_t s_range[2];
-  const int tid = threadIdx.x, wid = tid >> 6;
+  // inclusive offsets of the workgroup's Gaussians: those holding its pairs
+  // (at most kDupPairs, each holds one or more) and possibly the next one
+  __shared__ uint32_t s_end[kDupPairs + 1];
+  const int tid = threadIdx.x;
   const uint32_t p0 = blockIdx.x * (uint32_t)kDupPairs;
   const uint32_t p1 = min(p0 + (uint32_t)kDupPairs, n_pairs) - 1;  // last pair of the workgroup
-  if (wid < 2) {
-    const uint32_t r = wave_search_gt(offsets, n_vis, wid == 0 ? p0 : p1);
-    if ((tid & 63) == 0) s_range[wid] = r;
-  }
-  __syncthreads();
-  const uint32_t r_lo = s_range[0], r_hi = s_range[1];  // r_hi - r_lo < kDupPairs: each holds >= 1 pair
-  const uint32_t cnt = min(r_hi - r_lo + 1, (uint32_t)kDupPairs);
+  // the Gaussians holding pair p0 and the next workgroup's first pair (or the
+  // last visible one): the one holding p1 lies between them
+  const uint32_t r_lo = min(dup_first[blockIdx.x], n_vis - 1);
+  const uint32_t r_hi = blockIdx.x + 1 < gridDim.x ? min(dup_first[blockIdx.x + 1], n_vis - 1) : n_vis - 1;
+  const uint32_t cnt = min(r_hi >= r_lo ? r_hi - r_lo + 1 : 1u, (uint32_t)kDupPairs + 1);
   for (uint32_t i = tid; i < cnt; i += kDupThreads) s_end[i] = offsets[r_lo + i];
   const uint32_t start_lo = r_lo > 0 ? offsets[r_lo - 1] : 0u;  // first pair of Gaussian r_lo
   __syncthreads();
@@ -133,13 +104,16 @@ __global__ void fill_u64_kernel(unsigned long long* __restrict__ p, unsigned lon
 
 }  // namespace
 
-hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* order, const uint2* tile_rect, int64_t n_vis,
-                            int64_t n_pairs, int32_t tiles_x, uint32_t* tile_keys, uint32_t* vals,
-                            hipStream_t stream) {
+int64_t duplicate_blocks(int64_t n_pairs) { return (n_pairs + kDupPairs - 1) / kDupPairs; }
+
+// dup_first: per workgroup, written by launch_inclusive_sum over the same offsets
+hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* dup_first, const uint32_t* order,
+                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
+                            uint32_t* tile_keys, uint32_t* vals, hipStream_t stream) {
   if (n_pairs <= 0 || n_vis <= 0) return hipSuccess;
   if (n_pairs >= (int64_t)1 << 32 || n_vis >= (int64_t)1 << 32) return hipErrorInvalidValue;
-  duplicate_kernel<<<dim3((unsigned)((n_pairs + kDupPairs - 1) / kDupPairs)), kDupThreads, 0, stream>>>(
-      offsets, order, tile_rect, (uint32_t)n_vis, (uint32_t)n_pairs, tiles_x, tile_keys, vals);
+  duplicate_kernel<<<dim3((unsigned)duplicate_blocks(n_pairs)), kDupThreads, 0, stream>>>(
+      offsets, dup_first, order, tile_rect, (uint32_t)n_vis, (uint32_t)n_pairs, tiles_x, tile_keys, vals);
   return hipGetLastError();
 }
 

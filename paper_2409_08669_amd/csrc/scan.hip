@@ -3,7 +3,10 @@
 // depth sort's last pass writes tiles_touched in that order).
 // Reduce-then-scan in two launches: per-block totals, then each block adds up
 // the totals of the blocks before it (a few hundred words, read from L2) and
-// rescans its 2048 entries from that prefix.
+// rescans its 2048 entries from that prefix. The rescan also records, for
+// every chunk of kDupPairs pairs, the Gaussian whose pairs [out[r-1], out[r])
+// hold the chunk's first pair, so that each DuplicateWithKeys workgroup finds
+// its Gaussians with one load instead of a search.
 #include "adr_internal.h"
 
 namespace adr {
@@ -52,7 +55,8 @@ __global__ void __launch_bounds__(kScanThreads) block_totals_kernel(const uint32
 
 __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_t* __restrict__ in, int64_t n,
                                                                    const uint32_t* __restrict__ partials,
-                                                                   uint32_t* __restrict__ out) {
+                                                                   uint32_t* __restrict__ out,
+                                                                   uint32_t* __restrict__ dup_first) {
   __shared__ uint32_t smem[4];
   const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
@@ -71,8 +75,14 @@ __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_
   uint32_t run = prefix + incl - s;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
+    const uint32_t before = run;
     run += v[i];
-    if (base + i < n) out[base + i] = run;
+    if (base + i < n) {
+      out[base + i] = run;
+      // chunks c whose first pair c * kDupPairs lies in [before, run)
+      for (uint64_t c = ((uint64_t)before + kDupPairs - 1) / kDupPairs; c * kDupPairs < run; ++c)
+        dup_first[c] = (uint32_t)(base + i);
+    }
   }
 }
 
@@ -80,12 +90,13 @@ __global__ void __launch_bounds__(kScanThreads) scan_blocks_kernel(const uint32_
 
 int64_t inclusive_sum_partials(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
 
+// dup_first: duplicate_blocks(total of in) words
 hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
-                                hipStream_t stream) {
+                                uint32_t* dup_first, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = inclusive_sum_partials(n);
   block_totals_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials);
-  scan_blocks_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials, out);
+  scan_blocks_kernel<<<dim3((unsigned)nb), kScanThreads, 0, stream>>>(in, n, partials, out, dup_first);
   return hipGetLastError();
 }
 
