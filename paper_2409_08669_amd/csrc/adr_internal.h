@@ -196,8 +196,14 @@ hipError_t launch_pack_scene(const adr_scene_desc& desc, const float* means, con
                              hipStream_t stream);
 hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_sums, hipStream_t stream);
 int64_t preprocess_blocks(int64_t n);
+// Frames whose tile ranges have at most this many words have them cleared
+// (with the counters and the load sums) by the kernel that follows
+// Preprocess instead of a launch of their own.
+constexpr int64_t kNotifyClearMax = (int64_t)1 << 17;
+// n_ranges, load_sums: what the frame-init launch clears, cleared here when
+// 0 < n_ranges <= kNotifyClearMax (n_ranges = 0: nothing is cleared)
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
-                             hipStream_t stream);
+                             int64_t n_ranges, uint64_t* load_sums, hipStream_t stream);
 hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
                                 uint32_t* dup_first, hipStream_t stream);
 int64_t inclusive_sum_partials(int64_t n);

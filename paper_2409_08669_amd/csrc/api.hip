@@ -298,11 +298,14 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ws->last_stream = stream;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[0], stream));
 
-  // Clear the frame's counters, histograms, load partials and tile ranges.
-  ADR_HIP(launch_frame_init(ws, n_tiles, out->load_sums, stream));
+  // Clear the frame's counters, load sums and tile ranges: in the kernel that
+  // follows Preprocess when there is one and the ranges are small enough,
+  // else with a launch of their own.
+  const bool clear_in_notify = s.n > 0 && 2 * n_tiles <= kNotifyClearMax;
+  if (!clear_in_notify) ADR_HIP(launch_frame_init(ws, n_tiles, out->load_sums, stream));
   // Stage 1: Preprocess (+ pair total and visible count)
   ws->frame_seq += 1;
-  ADR_HIP(launch_preprocess(s, ca, cu, ws, stream));
+  ADR_HIP(launch_preprocess(s, ca, cu, ws, clear_in_notify ? 2 * n_tiles : 0, out->load_sums, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
   // The pair count sizes everything after this point. The last Preprocess
   // workgroup writes it to mapped host memory; wait for this frame's number.

@@ -366,11 +366,23 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
 // workgroup's partials visible): reduces them into the frame counters and
 // hands the pair count, the visible count and the visible depth-key range to
 // the host through mapped pinned memory, then publishes the frame's number.
+// It also clears what the rest of the frame accumulates into (the tile
+// ranges, the blend's FP64 counters, the caller's load sums) when n_ranges > 0.
 __global__ void __launch_bounds__(1024) notify_host_kernel(const ulonglong4* __restrict__ block_parts, int nb,
                                                            unsigned long long* __restrict__ counters,
                                                            unsigned long long* __restrict__ notify,
-                                                           unsigned long long seq) {
+                                                           unsigned long long seq, uint32_t* __restrict__ ranges,
+                                                           int64_t n_ranges,
+                                                           unsigned long long* __restrict__ load_sums) {
   __shared__ unsigned long long red[4][16];
+  for (int64_t i = threadIdx.x; i < n_ranges; i += blockDim.x) ranges[i] = 0u;
+  if (n_ranges > 0) {
+    if (threadIdx.x == 0) {
+      counters[kCntBand] = 0ull;
+      counters[kCntReplay] = 0ull;
+    }
+    if (load_sums && threadIdx.x < 4) load_sums[threadIdx.x] = 0ull;
+  }
   unsigned long long t = 0, v = 0, mn = ~0ull, mx = 0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
     const ulonglong4 r = block_parts[i];
@@ -700,7 +712,7 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
 int64_t preprocess_blocks(int64_t n) { return (n + 255) / 256; }
 
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
-                             hipStream_t stream) {
+                             int64_t n_ranges, uint64_t* load_sums, hipStream_t stream) {
   if (s.n == 0) return hipSuccess;
   static const ShConsts shc = make_sh_consts();
   const int64_t nb = preprocess_blocks(s.n);
@@ -709,8 +721,10 @@ hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const Cul
                                                             cam, cull, ws->rec, ws->exact, ws->tile_rect,
                                                             ws->depth.keys[0], ws->depth.vals[0], ws->touched,
                                                             ws->block_parts);
+  if (n_ranges > kNotifyClearMax) return hipErrorInvalidValue;
   notify_host_kernel<<<1, 1024, 0, stream>>>(ws->block_parts, (int)nb, ws->dev_counters, ws->notify_dev,
-                                             ws->frame_seq);
+                                             ws->frame_seq, ws->ranges, n_ranges,
+                                             (unsigned long long*)load_sums);
   return hipGetLastError();
 }
 

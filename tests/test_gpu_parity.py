@@ -335,6 +335,33 @@ def test_4k_frame_integer_stage_and_sampled_tiles(P, ws):
     np.testing.assert_array_equal(b["l_blend"], g["l_blend"])
 
 
+def test_frame_of_more_than_65536_tiles(P, ws):
+    """4608x4096 (73728 tiles, 50k Gaussians), a tile grid larger than any
+    of the workloads': the integer stage bit-exact, 34 sampled tiles
+    (corners, busiest, seeded) against the oracle, and the frame's l_iter sum
+    equal to the one in its load sums."""
+    s = scene_clusters(50_000, seed=4)
+    cam = camera_orbit(14.0, 35.0, 120.0, 4608, 4096)
+    sg = P.Scene.from_synth(s)
+    pre = O.preprocess(s, cam, O.Params())
+    params = oracle_params(2)
+    rects = O.tile_rects(pre, cam, params)
+    keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+    ranges = O.tile_ranges(keys, cam)
+    tx_n, ty_n = O.n_tiles(cam)
+    assert tx_n * ty_n > 65536
+    say("50k G 4608x4096 AABB")
+    g = gpu_frame(P, ws, sg, cam, 2)
+    o = dict(tiles_touched=rects["tiles_touched"], n_pairs=int(keys.size), keys=keys, values=values, ranges=ranges)
+    check_integer_stage(g, o, s.n)
+    busy = np.argsort(ranges[:, 1] - ranges[:, 0])[-8:]
+    rng = np.random.default_rng(14)
+    tiles = np.unique(np.concatenate([rng.choice(tx_n * ty_n, 24, replace=False), busy, [0, tx_n * ty_n - 1]]))
+    r = O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+    check_pixels(g, r, mask=r["done"])
+    assert int(g["load_sums"][2]) == int(g["l_iter"].astype(np.int64).sum())
+
+
 @pytest.mark.slow
 def test_load_imbalanced_scene_exact_and_capped(P, ws):
     """3M Gaussians with 20% in 8 dense clusters, 1600x1040, first pose of the
