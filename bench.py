@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--cpu-tiles", type=int, default=2048)
     ap.add_argument("--train-iters", type=int, default=600, help="iterations per run of --only train")
-    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb"],
+    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb", "seeds"],
                     default=None,
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
@@ -132,6 +132,13 @@ def measured_traffic(kernel):
 
 def main():
     args = parse()
+    if args.only == "seeds":
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        import paper_2409_08669_amd as P
+        P.load()
+        print(json.dumps({"mode": "seeds", "seeds": seed_sweep(P, args)}), flush=True)
+        return
     if args.only == "lb":
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -416,6 +423,49 @@ def _ssim(img, ref):
     c1, c2 = 0.01 ** 2, 0.03 ** 2
     m = ((2 * mu_a * mu_b + c1) * (2 * s_ab + c2)) / ((mu_a * mu_a + mu_b * mu_b + c1) * (s_aa + s_bb + c2))
     return m.mean()
+
+
+def seed_sweep(P, args):
+    """The headline workload (1M Gaussians, SH3, 1920x1080 orbit camera) for
+    scene seeds 0, 1 and 2: frames/s (back-to-back frames after warm-up) and
+    pairs per frame of the three cull modes, and whether their images are
+    bitwise identical."""
+    import torch
+    from synth import scene_clusters, camera_1080p
+
+    cam = camera_1080p()
+    w, h = cam.width, cam.height
+    dev = "cuda"
+    out = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
+               l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
+               l_blend=torch.empty((h, w), dtype=torch.int32, device=dev),
+               load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
+    ws = P.Workspace()
+    res = []
+    for seed in (0, 1, 2):
+        log(f"seed sweep: scene seed {seed}")
+        sg = P.Scene.from_synth(scene_clusters(args.n, seed=seed))
+        row = {"seed": seed}
+        images = []
+        for name, mode in (("3sigma", P.ADR_CULL_3SIGMA), ("adaptive", P.ADR_CULL_ADAPTIVE), ("aabb", P.ADR_CULL_AABB)):
+            params = P.RenderParams(cull=mode)
+            for _ in range(args.warmup):
+                P.render(sg, cam, params, ws, **out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                n_pairs = P.render(sg, cam, params, ws, **out)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            row[name] = {"fps": round(1.0 / dt, 2), "pairs": int(n_pairs)}
+            images.append(out["image"].clone())
+        row["identical_images"] = all(bool(torch.equal(images[0], im)) for im in images[1:])
+        row["speedup_aabb_vs_3sigma"] = round(row["aabb"]["fps"] / row["3sigma"]["fps"], 4)
+        res.append(row)
+        log(f"seed {seed}: " + ", ".join(f"{k} {row[k]['fps']:.1f} frames/s {row[k]['pairs']} pairs"
+                                        for k in ("3sigma", "adaptive", "aabb")) + f", identical {row['identical_images']}")
+        del sg
+    return res
 
 
 def cap_sweep(P, args):
