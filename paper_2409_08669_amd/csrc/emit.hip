@@ -81,6 +81,8 @@ __global__ void __launch_bounds__(256) compose_keys_kernel(const uint32_t* __res
 
 // Clears everything a frame accumulates into: counters, sort histograms,
 // the caller's load sums and the tile ranges (empty tiles keep (0, 0)).
+// Used when the kernel after Preprocess cannot do it: an empty scene (no
+// Preprocess) or more tile-range words than that one workgroup clears.
 __global__ void __launch_bounds__(256) frame_init_kernel(unsigned long long* __restrict__ counters,
                                                          uint32_t* __restrict__ hists,
                                                          unsigned long long* __restrict__ load_sums,
@@ -117,7 +119,8 @@ hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* dup_first, 
   return hipGetLastError();
 }
 
-// ranges must be zero on entry (the frame-init kernel clears them)
+// ranges must be zero on entry (cleared at the start of the frame, by the
+// kernel after Preprocess or by the frame-init kernel)
 hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream) {
   if (n_pairs <= 0) return hipSuccess;

@@ -662,14 +662,14 @@ finished:
   if (counters) {
     const unsigned long long nbd = wave_sum_u64(px.n_rare & 0xffffu), nrp = wave_sum_u64(px.n_rare >> 16);
     if (lane == 0) {
-      if (nbd) atomicAdd(&counters[2], nbd);
-      if (nrp) atomicAdd(&counters[3], nrp);
+      if (nbd) atomicAdd(&counters[kCntBand], nbd);
+      if (nrp) atomicAdd(&counters[kCntReplay], nrp);
     }
   }
 }
 
-// Adds the per-wave partials into the four load sums (zeroed by the
-// frame-init kernel). Integer sums: the result does not depend on the order.
+// Adds the per-wave partials into the four load sums (zeroed at the start of
+// the frame). Integer sums: the result does not depend on the order.
 __global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __restrict__ wave_sums, int n,
                                                         unsigned long long* __restrict__ out) {
   __shared__ unsigned long long part[4][4];
