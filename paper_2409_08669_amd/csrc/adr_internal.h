@@ -107,6 +107,7 @@ struct SortBuffers {
 
 struct adr_scene {
   adr::DeviceScene d;
+  uint64_t uid = 0;  // unique per created scene in this process (a freed scene's address may be reused)
 };
 
 struct adr_workspace {
@@ -157,6 +158,7 @@ struct adr_workspace {
   int32_t last_depth_bits = 0;  // key bits the last frame's depth sort covered
   // the last frame rendered on this workspace (what adr_render_backward differentiates)
   const adr_scene* last_scene = nullptr;
+  uint64_t last_scene_uid = 0;
   adr_camera last_cam{};
   adr_render_params last_params{};
   const uint32_t* last_vals = nullptr;  // its sorted Gaussian ids

@@ -270,6 +270,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
                                  adr_frame* out, adr_workspace* ws, void* stream_ptr) {
   adr_status st = validate(scene, cam, p, out, ws);
   if (st != ADR_OK) return st;
+  ws->last_vals = nullptr;  // no frame to differentiate until this one is enqueued whole
   hipStream_t stream = (hipStream_t)stream_ptr;
   const DeviceScene& s = scene->d;
   const int W = cam->width, H = cam->height;
@@ -388,6 +389,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, n_pairs, s.n, ca, bl, out, ws,
                         stream));
   ws->last_scene = scene;
+  ws->last_scene_uid = scene->uid;
   ws->last_cam = *cam;
   ws->last_params = *p;
   ws->last_vals = vals;
@@ -447,7 +449,8 @@ extern "C" adr_status adr_render_backward_load(const adr_scene* scene, const adr
     set_error("adr_render_backward: dl_dimage, grads, and the forward frame's final_t and l_iter are required");
     return ADR_E_INVALID;
   }
-  if (ws->last_scene != scene || !same_camera(ws->last_cam, *cam) || !same_params(ws->last_params, *p) ||
+  if (ws->last_scene != scene || ws->last_scene_uid != scene->uid || !same_camera(ws->last_cam, *cam) ||
+      !same_params(ws->last_params, *p) ||
       !ws->last_vals) {
     set_error("adr_render_backward: the last adr_render on this workspace was not this scene, camera and params");
     return ADR_E_INVALID;

@@ -4,6 +4,7 @@
 // float planes so a wave reads 64 consecutive floats per coefficient.
 #include "adr_internal.h"
 
+#include <atomic>
 #include <new>
 
 namespace adr {
@@ -68,11 +69,13 @@ extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** o
     set_error("adr_create_scene: NULL array with n > 0");
     return ADR_E_INVALID;
   }
+  static std::atomic<uint64_t> next_uid{1};
   adr_scene* s = new (std::nothrow) adr_scene();
   if (!s) {
     set_error("adr_create_scene: host allocation failed");
     return ADR_E_OOM;
   }
+  s->uid = next_uid.fetch_add(1);
   DeviceScene& d = s->d;
   d.n = desc->n;
   d.sh_degree = desc->sh_degree;
