@@ -344,6 +344,28 @@ def test_4k_frame_integer_stage_and_sampled_tiles(P, ws):
     np.testing.assert_array_equal(b["l_blend"], g["l_blend"])
 
 
+@pytest.mark.slow
+def test_4k_frame_3sigma_integer_stage(P, ws):
+    """The same 4K frame with 3-sigma culling: ~20.4M Gaussian-tile pairs,
+    the largest pair count of the tests. Tiles touched, pair count, sorted
+    keys and ids and tile ranges bit-exact against the oracle, and the image
+    bitwise the AABB one."""
+    s = scene_clusters(1_000_000, seed=1)
+    cam = camera_orbit(14.0, 35.0, 200.0, 3840, 2160)
+    sg = P.Scene.from_synth(s)
+    pre = O.preprocess(s, cam, O.Params())
+    params = oracle_params(0)
+    rects = O.tile_rects(pre, cam, params)
+    keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+    ranges = O.tile_ranges(keys, cam)
+    say(f"1M G 3840x2160 3-sigma, {keys.size} pairs")
+    g = gpu_frame(P, ws, sg, cam, 0)
+    o = dict(tiles_touched=rects["tiles_touched"], n_pairs=int(keys.size), keys=keys, values=values, ranges=ranges)
+    check_integer_stage(g, o, s.n)
+    a = gpu_frame(P, ws, sg, cam, 2, debug=False)
+    np.testing.assert_array_equal(g["image"], a["image"])
+
+
 def test_frame_of_more_than_65536_tiles(P, ws):
     """4608x4096 (73728 tiles, 50k Gaussians), a tile grid larger than any
     of the workloads': the integer stage bit-exact, 34 sampled tiles
