@@ -172,7 +172,10 @@ adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_r
  * Sec. 3.1) on the piece fixed by the forward's decisions; clamped alpha,
  * colour channels and EWA slopes pass no derivative.
  * Differentiates the frame of the last adr_render on ws, which must have had
- * the same scene, camera and params (ADR_E_INVALID otherwise); fwd is that
+ * the same scene (the same scene object: one destroyed and re-created does
+ * not match, even at the same address), camera and params, and must have
+ * enqueued its Render stage: a call that failed before it leaves nothing to
+ * differentiate (ADR_E_INVALID otherwise); fwd is that
  * call's frame, whose final_t and l_iter are required (each pixel walks its
  * list back to front from them: nothing else is stored per entry).
  * grads: caller-owned device arrays in the layout of adr_scene_desc (any may be
