@@ -427,9 +427,10 @@ def _ssim(img, ref):
 
 def seed_sweep(P, args):
     """The headline workload (1M Gaussians, SH3, 1920x1080 orbit camera) for
-    scene seeds 0, 1 and 2: frames/s (back-to-back frames after warm-up) and
-    pairs per frame of the three cull modes, and whether their images are
-    bitwise identical."""
+    scene seeds 0, 1 and 2: frames/s (back-to-back frames after warm-up),
+    pairs per frame, list entries examined and blended (the load sums) and the
+    blend's FP64 fallbacks of the three cull modes, and whether their images
+    are bitwise identical."""
     import torch
     from synth import scene_clusters, camera_1080p
 
@@ -457,7 +458,11 @@ def seed_sweep(P, args):
                 n_pairs = P.render(sg, cam, params, ws, **out)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / args.steps
-            row[name] = {"fps": round(1.0 / dt, 2), "pairs": int(n_pairs)}
+            sums = out["load_sums"].cpu().numpy()
+            cnt = ws.counters()
+            row[name] = {"fps": round(1.0 / dt, 2), "pairs": int(n_pairs), "examined": int(sums[2]),
+                         "blended": int(sums[0]), "t_replays": cnt.get("t_replays"),
+                         "band_redecisions": cnt.get("band_redecisions")}
             images.append(out["image"].clone())
         row["identical_images"] = all(bool(torch.equal(images[0], im)) for im in images[1:])
         row["speedup_aabb_vs_3sigma"] = round(row["aabb"]["fps"] / row["3sigma"]["fps"], 4)
