@@ -431,6 +431,7 @@ def seed_sweep(P, args):
     pairs per frame, list entries examined and blended (the load sums) and the
     blend's FP64 fallbacks of the three cull modes, and whether their images
     are bitwise identical."""
+    import numpy as np
     import torch
     from synth import scene_clusters, camera_1080p
 
@@ -463,6 +464,14 @@ def seed_sweep(P, args):
             row[name] = {"fps": round(1.0 / dt, 2), "pairs": int(n_pairs), "examined": int(sums[2]),
                          "blended": int(sums[0]), "t_replays": cnt.get("t_replays"),
                          "band_redecisions": cnt.get("band_redecisions")}
+            if name == "aabb":  # load imbalance E_exec / E_alg of the 8 x 8 pixel waves
+                li = out["l_iter"].cpu().numpy().astype(np.int64)
+                hp, wp = -(-h // 8) * 8, -(-w // 8) * 8
+                pad = np.zeros((hp, wp), dtype=np.int64)
+                pad[:h, :w] = li
+                wave_max = pad.reshape(hp // 8, 8, wp // 8, 8).max(axis=(1, 3))
+                row[name]["E_exec_over_E_alg"] = round(float(64 * wave_max.sum() / max(li.sum(), 1)), 4)
+                row[name]["heaviest_wave_examined"] = int(wave_max.max())
             images.append(out["image"].clone())
         row["identical_images"] = all(bool(torch.equal(images[0], im)) for im in images[1:])
         row["speedup_aabb_vs_3sigma"] = round(row["aabb"]["fps"] / row["3sigma"]["fps"], 4)
