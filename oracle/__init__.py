@@ -14,6 +14,8 @@ from .adr_oracle import (  # noqa: F401
     cull_radii,
     n_tiles,
     sh_basis,
+    camera_position,
+    sh_to_rgb,
     preprocess,
     tile_rects,
     duplicate_and_sort,

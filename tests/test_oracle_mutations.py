@@ -44,6 +44,17 @@ MUTATIONS = [
      ["test_sh_basis_matches_scipy_complex_harmonics"]),
     ("load std as sample std", "var = (n * s2 - s1 * s1) / (n * n)", "var = (n * s2 - s1 * s1) / (n * (n - 1))",
      ["test_load_stats_closed_form"]),
+    ("camera centre +R^T t", "return -r.T @ t", "return r.T @ t",
+     ["test_camera_position_is_the_eye_of_a_rotated_camera",
+      "test_sh_degree_one_colour_follows_the_direction_from_the_camera"]),
+    ("SH direction from the Gaussian to the camera", "v = mu - camera_position(cam)[None, :]",
+     "v = camera_position(cam)[None, :] - mu",
+     ["test_sh_degree_one_colour_follows_the_direction_from_the_camera"]),
+    ("EWA clamp of x uses the height", "lim_x = params.ewa_clamp * (cam.width / 2.0) / fx",
+     "lim_x = params.ewa_clamp * (cam.height / 2.0) / fx",
+     ["test_ewa_jacobian_is_clamped_off_screen"]),
+    ("EWA clamp removed", "xt = zs * np.clip(p[:, 0] / zs, -lim_x, lim_x)", "xt = p[:, 0]",
+     ["test_ewa_jacobian_is_clamped_off_screen"]),
 ]
 
 

@@ -160,6 +160,71 @@ def test_ewa_matches_numerical_jacobian_off_axis():
         np.testing.assert_allclose(pre["cov2"][g], [cov[0, 0], cov[0, 1], cov[1, 1]], rtol=1e-6, atol=1e-9)
 
 
+def _rotated_camera(eye, seed, w=128, h=96, f=60.0):
+    """A camera with a random orientation R whose centre is at `eye`:
+    p_cam = R p + t with t = -R eye, so that p = eye maps to the origin."""
+    r = Rotation.random(random_state=seed).as_matrix()
+    t = -r @ np.asarray(eye, dtype=np.float64)
+    return Camera(np.concatenate([r, t[:, None]], axis=1), f, f, w / 2.0, h / 2.0, w, h, 0.2)
+
+
+def test_camera_position_is_the_eye_of_a_rotated_camera():
+    for seed, eye in enumerate(([2.0, -1.0, -5.0], [0.0, 0.0, 7.5], [-3.0, 4.0, 0.25])):
+        cam = _rotated_camera(eye, seed)
+        np.testing.assert_allclose(O.camera_position(cam), eye, atol=1e-12)
+
+
+def test_sh_degree_one_colour_follows_the_direction_from_the_camera():
+    """Degree-1 colour in closed form, with the viewing direction written
+    out from the camera's eye (not from its [R | t]): channel 0 carries only
+    the m = 1 coefficient (Y = -k x), channel 1 only m = 0 (Y = k z), channel 2
+    only m = -1 (Y = -k y), k = sqrt(3 / (4 pi)); colour = 1/2 + coef Y."""
+    k = math.sqrt(3.0 / (4.0 * math.pi))
+    rng = np.random.default_rng(21)
+    for seed, eye in enumerate(([2.0, -1.0, -5.0], [-4.0, 3.0, 1.0])):
+        cam = _rotated_camera(eye, 10 + seed)
+        means = rng.uniform(-1.5, 1.5, size=(6, 3))
+        sh = np.zeros((6, 4, 3))
+        sh[:, 3, 0] = 0.7   # m = +1 -> red
+        sh[:, 2, 1] = -0.6  # m = 0  -> green
+        sh[:, 1, 2] = 0.5   # m = -1 -> blue
+        scene = one_scene(means, [[-2.0] * 3] * 6, [[1, 0, 0, 0]] * 6, [0.0] * 6, sh=sh, degree=1)
+        col = O.preprocess(scene, cam, O.Params())["color"]
+        v = scene.means.astype(np.float64) - np.asarray(eye)[None, :]
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        sh32 = scene.sh.astype(np.float64)
+        expect = np.stack([0.5 + sh32[:, 3, 0] * (-k * v[:, 0]),
+                           0.5 + sh32[:, 2, 1] * (k * v[:, 2]),
+                           0.5 + sh32[:, 1, 2] * (-k * v[:, 1])], axis=1)
+        np.testing.assert_allclose(col, np.maximum(expect, 0.0), atol=1e-12)
+
+
+def test_ewa_jacobian_is_clamped_off_screen():
+    """Centres beyond the EWA clamp: the Jacobian is taken at x/z (or y/z)
+    clamped to +-1.3 (W/2)/fx (or (H/2)/fy), written out here by hand, on a
+    camera with W != H so that the two limits differ. Camera at the origin,
+    no rotation, isotropic Sigma = s^2 I, so Sigma' = s^2 J J^T + 0.3 I."""
+    w, h, f = 128, 64, 40.0
+    cam = Camera(np.array([[1.0, 0, 0, 0], [0, 1.0, 0, 0], [0, 0, 1.0, 0]]), f, f, w / 2.0, h / 2.0, w, h, 0.2)
+    lim_x, lim_y = 1.3 * (w / 2) / f, 1.3 * (h / 2) / f  # 2.08 and 1.04
+    # beyond the x limit; beyond the -y limit; inside both
+    pts = np.array([[5.0, 0.5, 2.0], [0.5, -3.0, 2.0], [0.8, 0.4, 2.0]])
+    scene = one_scene(pts, [[-1.0] * 3] * 3, [[1, 0, 0, 0]] * 3, [0.0] * 3)
+    cov = O.preprocess(scene, cam, O.Params())["cov2"]
+    s2 = math.exp(-1.0) ** 2
+    m = scene.means.astype(np.float64)  # the float32 centres the scene holds
+    xt = [2.0 * lim_x, m[1, 0], m[2, 0]]  # clamped x/z times z (first point only)
+    yt = [m[0, 1], -2.0 * lim_y, m[2, 1]]  # clamped y/z times z (second point only)
+    for g in range(3):
+        z = 2.0
+        jx = np.array([f / z, 0.0, -f * xt[g] / z ** 2])
+        jy = np.array([0.0, f / z, -f * yt[g] / z ** 2])
+        a = s2 * jx @ jx + 0.3
+        b = s2 * jx @ jy
+        c = s2 * jy @ jy + 0.3
+        np.testing.assert_allclose(cov[g], [a, b, c], rtol=1e-13, atol=1e-13, err_msg=f"point {g}")
+
+
 def test_tiny_gaussian_projects_to_lowpass_only():
     s = one_scene([[0.1, 0.1, 0.0]], [[-30, -30, -30]], [[1, 0, 0, 0]], [0.0])
     pre = O.preprocess(s, axis_camera(), O.Params())
