@@ -210,7 +210,9 @@ int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
  * must have finished): [0] pairs, [1] visible Gaussians (tiles_touched > 0),
  * [2] exact-band alpha re-decisions, [3] exact-band transmittance replays,
  * [4] key bits the depth sort of the Gaussians covered (the visible depth
- * keys' range; 8 per radix pass). Returns the number of entries written. */
+ * keys' range; 8 per radix pass), [5] sort values or output positions found
+ * out of range and dropped (always 0 unless a kernel is wrong; a dropped value
+ * is never used as an index). Returns the number of entries written. */
 int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n);
 
 /* Serving: resident scenes, concurrent requests.

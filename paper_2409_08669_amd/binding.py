@@ -259,9 +259,9 @@ class Workspace:
         return {STAGES[i]: float(buf[i]) for i in range(k)}
 
     def counters(self) -> dict:
-        buf = (ctypes.c_int64 * 5)()
-        k = load().adr_workspace_counters(self._h, buf, 5)
-        names = ("pairs", "visible", "band_redecisions", "t_replays", "depth_sort_bits")
+        buf = (ctypes.c_int64 * 6)()
+        k = load().adr_workspace_counters(self._h, buf, 6)
+        names = ("pairs", "visible", "band_redecisions", "t_replays", "depth_sort_bits", "bad_sort_indices")
         return {names[i]: int(buf[i]) for i in range(k)}
 
     def close(self):

@@ -175,6 +175,7 @@ constexpr int kCntBand = 2;        // FP64 re-decisions near alpha_low
 constexpr int kCntReplay = 3;      // FP64 transmittance replays near t_min
 constexpr int kCntDepthMin = 4;    // smallest depth key of a visible Gaussian
 constexpr int kCntDepthMax = 5;    // largest depth key of a visible Gaussian
+constexpr int kCntBadIndex = 6;    // sort values or positions out of range (0 unless a kernel is wrong)
 constexpr int kNotifySlots = 8;    // mapped words: pairs, visible, frame number, depth min, depth max
 constexpr int kCounterSlots = 8;
 constexpr int kHistWords = 4 * 256;  // digit histograms of up to four 8-bit passes
@@ -211,17 +212,18 @@ hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, ui
 int64_t inclusive_sum_partials(int64_t n);
 int64_t duplicate_blocks(int64_t n_pairs);
 hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* dup_first, const uint32_t* order,
-                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
+                            const uint2* tile_rect, int64_t n_vis, int64_t n_gauss, int64_t n_pairs, int32_t tiles_x,
                             uint32_t* tile_keys, uint32_t* vals, hipStream_t stream);
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
                              uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
-                             hipStream_t stream, const uint32_t* gather_src = nullptr,
-                             uint32_t* gather_dst = nullptr);
+                             hipStream_t stream, unsigned long long* bad_count,
+                             const uint32_t* gather_src = nullptr, uint32_t* gather_dst = nullptr,
+                             int64_t gather_n = 0);
 int64_t sort_scratch_entries(int64_t n);
 hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* ranges, int32_t n_tiles,
                               hipStream_t stream);
 hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, const RenderRecord* rec,
-                               int64_t n_pairs, uint64_t* keys, hipStream_t stream);
+                               int64_t n_pairs, int64_t n_gauss, uint64_t* keys, hipStream_t stream);
 int64_t tile_order_scratch(int n_tiles);
 hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order, uint32_t* counts,
                              hipStream_t stream);

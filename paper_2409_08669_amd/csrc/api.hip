@@ -360,7 +360,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     const uint32_t lim = dbits >= 32 ? 0xffffffffu : (uint32_t)((1ull << dbits) - 1);
     // the last pass also lays tiles_touched out in depth order for the scan
     ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, dbits, (uint32_t)dmin, lim, ws->sort_scratch,
-                              ws->hists, &dsorted, stream, ws->touched, ws->touched_sorted));
+                              ws->hists, &dsorted, stream, ws->dev_counters + kCntBadIndex, ws->touched,
+                              ws->touched_sorted, s.n));
     if (s.n == 1)  // nothing to sort: the one Gaussian is its own order
       ADR_HIP(hipMemcpyAsync(ws->touched_sorted, ws->touched, sizeof(uint32_t), hipMemcpyDeviceToDevice, stream));
   }
@@ -370,13 +371,14 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   ADR_HIP(launch_inclusive_sum(ws->touched_sorted, ws->offsets, n_vis, ws->scan_partials, ws->dup_first, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[4], stream));
   // Stage 3: DuplicateWithKeys, in depth order, keyed by tile id
-  ADR_HIP(launch_duplicate(ws->offsets, ws->dup_first, order, ws->tile_rect, n_vis, n_pairs, ca.tiles_x, ws->pairs.keys[0],
-                           ws->pairs.vals[0], stream));
+  ADR_HIP(launch_duplicate(ws->offsets, ws->dup_first, order, ws->tile_rect, n_vis, s.n, n_pairs, ca.tiles_x,
+                           ws->pairs.keys[0], ws->pairs.vals[0], stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[5], stream));
   // Stage 4b: stable sort by tile id; equal tiles keep the depth order
   int psorted = 0;
   ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), 0u, 0xffffffffu,
-                            ws->sort_scratch, ws->hists + kHistWords, &psorted, stream));
+                            ws->sort_scratch, ws->hists + kHistWords, &psorted, stream,
+                            ws->dev_counters + kCntBadIndex));
   const uint32_t* tiles = ws->pairs.keys[psorted];
   const uint32_t* vals = ws->pairs.vals[psorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
@@ -412,7 +414,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
       set_error("adr_render: pair_capacity smaller than the frame's pair count (see n_pairs)");
       return ADR_E_WORKSPACE;
     }
-    if (out->keys) ADR_HIP(launch_compose_keys(tiles, vals, ws->rec, n_pairs, out->keys, stream));
+    if (out->keys) ADR_HIP(launch_compose_keys(tiles, vals, ws->rec, n_pairs, s.n, out->keys, stream));
     if (out->values && n_pairs > 0)
       ADR_HIP(hipMemcpyAsync(out->values, vals, (size_t)n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                              stream));
@@ -501,8 +503,8 @@ extern "C" int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32
     (void)hipGetLastError();
     return 0;
   }
-  const int idx[5] = {kCntPairs, kCntVisible, kCntBand, kCntReplay, -1};
+  const int idx[6] = {kCntPairs, kCntVisible, kCntBand, kCntReplay, -1, kCntBadIndex};
   int32_t k = 0;
-  for (; k < 5 && k < n; ++k) out[k] = idx[k] >= 0 ? (int64_t)ws->host_counters[idx[k]] : ws->last_depth_bits;
+  for (; k < 6 && k < n; ++k) out[k] = idx[k] >= 0 ? (int64_t)ws->host_counters[idx[k]] : ws->last_depth_bits;
   return k;
 }

@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(kDupThreads) duplicate_kernel(const uint32_t* 
                                                                 const uint32_t* __restrict__ dup_first,
                                                                 const uint32_t* __restrict__ order,
                                                                 const uint2* __restrict__ tile_rect, uint32_t n_vis,
-                                                                uint32_t n_pairs, int32_t tiles_x,
+                                                                uint32_t n_gauss, uint32_t n_pairs, int32_t tiles_x,
                                                                 uint32_t* __restrict__ tile_keys,
                                                                 uint32_t* __restrict__ vals) {
   // inclusive offsets of the workgroup's Gaussians: those holding its pairs
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kDupThreads) duplicate_kernel(const uint32_t* 
     }
     const uint32_t first = lo > 0 ? s_end[lo - 1] : start_lo;
     const uint32_t k = p - first;
-    const uint32_t g = order[r_lo + lo];
+    const uint32_t g = min(order[r_lo + lo], n_gauss - 1);  // (a sorted id is always below n_gauss)
     const uint2 r = tile_rect[g];
     const uint32_t tx_lo = r.x & 0xffffu, tx_hi = r.x >> 16;
     const uint32_t ty_lo = r.y & 0xffffu;
@@ -73,10 +73,10 @@ __global__ void __launch_bounds__(256) tile_ranges_kernel(const uint32_t* __rest
 __global__ void __launch_bounds__(256) compose_keys_kernel(const uint32_t* __restrict__ tiles,
                                                            const uint32_t* __restrict__ vals,
                                                            const RenderRecord* __restrict__ rec, int64_t n_pairs,
-                                                           uint64_t* __restrict__ keys) {
+                                                           uint32_t n_gauss, uint64_t* __restrict__ keys) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pairs) return;
-  keys[p] = ((uint64_t)tiles[p] << 32) | rec[vals[p]].depth_key;
+  keys[p] = ((uint64_t)tiles[p] << 32) | rec[min(vals[p], n_gauss - 1)].depth_key;
 }
 
 // Clears everything a frame accumulates into: counters, sort histograms,
@@ -110,12 +110,13 @@ int64_t duplicate_blocks(int64_t n_pairs) { return (n_pairs + kDupPairs - 1) / k
 
 // dup_first: per workgroup, written by launch_inclusive_sum over the same offsets
 hipError_t launch_duplicate(const uint32_t* offsets, const uint32_t* dup_first, const uint32_t* order,
-                            const uint2* tile_rect, int64_t n_vis, int64_t n_pairs, int32_t tiles_x,
+                            const uint2* tile_rect, int64_t n_vis, int64_t n_gauss, int64_t n_pairs, int32_t tiles_x,
                             uint32_t* tile_keys, uint32_t* vals, hipStream_t stream) {
   if (n_pairs <= 0 || n_vis <= 0) return hipSuccess;
-  if (n_pairs >= (int64_t)1 << 32 || n_vis >= (int64_t)1 << 32) return hipErrorInvalidValue;
+  if (n_pairs >= (int64_t)1 << 32 || n_vis > n_gauss || n_gauss >= (int64_t)1 << 32) return hipErrorInvalidValue;
   duplicate_kernel<<<dim3((unsigned)duplicate_blocks(n_pairs)), kDupThreads, 0, stream>>>(
-      offsets, dup_first, order, tile_rect, (uint32_t)n_vis, (uint32_t)n_pairs, tiles_x, tile_keys, vals);
+      offsets, dup_first, order, tile_rect, (uint32_t)n_vis, (uint32_t)n_gauss, (uint32_t)n_pairs, tiles_x, tile_keys,
+      vals);
   return hipGetLastError();
 }
 
@@ -130,10 +131,10 @@ hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* 
 }
 
 hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, const RenderRecord* rec,
-                               int64_t n_pairs, uint64_t* keys, hipStream_t stream) {
-  if (n_pairs <= 0) return hipSuccess;
+                               int64_t n_pairs, int64_t n_gauss, uint64_t* keys, hipStream_t stream) {
+  if (n_pairs <= 0 || n_gauss <= 0) return hipSuccess;
   compose_keys_kernel<<<dim3((unsigned)((n_pairs + 255) / 256)), 256, 0, stream>>>(tiles, vals, rec, n_pairs,
-                                                                                   keys);
+                                                                                   (uint32_t)n_gauss, keys);
   return hipGetLastError();
 }
 

@@ -380,6 +380,7 @@ __global__ void __launch_bounds__(1024) notify_host_kernel(const ulonglong4* __r
     if (threadIdx.x == 0) {
       counters[kCntBand] = 0ull;
       counters[kCntReplay] = 0ull;
+      counters[kCntBadIndex] = 0ull;
     }
     if (load_sums && threadIdx.x < 4) load_sums[threadIdx.x] = 0ull;
   }

@@ -119,7 +119,8 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
                                                              const uint32_t* __restrict__ offsets, int64_t nb,
                                                              const uint32_t* __restrict__ totals,
                                                              const uint32_t* __restrict__ gather_src,
-                                                             uint32_t* __restrict__ gather_dst) {
+                                                             uint32_t* __restrict__ gather_dst, uint32_t gather_n,
+                                                             unsigned long long* __restrict__ bad_count) {
   constexpr int kTileKeys = kThreads * kItems;
   __shared__ uint32_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
@@ -177,7 +178,10 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   wcnt[1][d] = c0;
   wcnt[2][d] = c0 + c1;
   wcnt[3][d] = c0 + c1 + c2;
-  blk_start[d] = block_excl_scan(c0 + c1 + c2 + c3, scan_tmp);  // contains the barrier
+  blk_start[d] = block_excl_scan(c0 + c1 + c2 + c3, scan_tmp);
+  // The scan's own barriers come before this write, and the placement below
+  // reads the starts of digits that other waves own: a barrier of its own.
+  __syncthreads();
 
   // Stable local order in LDS, then a coalesced scatter per digit run.
 #pragma unroll
@@ -197,11 +201,20 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
     const uint32_t key = skeys[i];
     const uint32_t dd = digit_of(key, km, shift);
     const uint32_t o = glob_base[dd] + (uint32_t)i - blk_start[dd];
-    if (o < (uint64_t)n) {  // always true for a correct ranking; keeps a fault impossible
+    if (o < (uint64_t)n) {  // always true for a correct ranking
       const uint32_t val = svals[i];
       kout[o] = key;
       vout[o] = val;
-      if (gather_dst) gather_dst[o] = gather_src[val];  // the caller's per-value array, in sorted order
+      if (gather_dst) {  // the caller's per-value array, in sorted order
+        if (val < gather_n) {
+          gather_dst[o] = gather_src[val];
+        } else {  // a value that cannot index the array: counted, never read
+          gather_dst[o] = 0u;
+          atomicAdd(bad_count, 1ull);
+        }
+      }
+    } else {
+      atomicAdd(bad_count, 1ull);
     }
   }
 }
@@ -216,13 +229,17 @@ int64_t sort_scratch_entries(int64_t n) {
 
 // Stable sort of (key, value) by min(key - bias, lim), whose n_bits low bits
 // are all that vary. totals: 256 words of scratch. If gather_dst is given,
-// the last pass also writes gather_dst[i] = gather_src[value i] (values must
-// index gather_src).
+// the last pass also writes gather_dst[i] = gather_src[value i] for values
+// below gather_n (gather_src's length). bad_count: a device counter that
+// every value at or past gather_n and every out-of-range output position
+// increments (0 for a correct ranking).
 hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, int n_bits, uint32_t bias,
                              uint32_t lim, uint32_t* scratch, uint32_t* totals, int* result_buffer,
-                             hipStream_t stream, const uint32_t* gather_src, uint32_t* gather_dst) {
+                             hipStream_t stream, unsigned long long* bad_count, const uint32_t* gather_src,
+                             uint32_t* gather_dst, int64_t gather_n) {
   *result_buffer = 0;
   if (n <= 1 || n_bits <= 0) return hipSuccess;
+  if (gather_dst && (!gather_src || gather_n <= 0 || gather_n > 0xffffffffll)) return hipErrorInvalidValue;
   const int n_pass = (n_bits + 7) / 8;
   if (n_pass > kMaxPasses) return hipErrorInvalidValue;
   const int items = sort_items(n);
@@ -240,12 +257,14 @@ hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, in
       upsweep_kernel<kSmallSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
       digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
       downsweep_kernel<kSmallSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd, (uint32_t)gather_n,
+          bad_count);
     } else {
       upsweep_kernel<kLargeSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
       digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
       downsweep_kernel<kLargeSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd);
+          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd, (uint32_t)gather_n,
+          bad_count);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
