@@ -46,11 +46,13 @@ def parse():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.0,
-                    help="measured length of the serving run (0 = skip; serving is switched off in this "
-                         "build); 2 s of warm-up come first")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="measured length of the serving run (0 = skip); 2 s of warm-up come first")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="Poisson arrival rate, requests/s")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8, help="requests in flight at once")
+    ap.add_argument("--serve-batch", type=int, default=16, help="frames per batched blend launch")
+    ap.add_argument("--serve-budget-gib", type=float, default=24.0,
+                    help="device memory admitted requests may reserve (GiB)")
     ap.add_argument("--cpu-tiles", type=int, default=2048)
     ap.add_argument("--train-iters", type=int, default=600, help="iterations per run of --only train")
     ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb", "seeds"],
@@ -176,7 +178,8 @@ def main():
     out = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
                l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
                l_blend=torch.empty((h, w), dtype=torch.int32, device=dev),
-               load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
+               load_sums=torch.zeros(4, dtype=torch.int64, device=dev),
+               load_stats=torch.zeros(4, dtype=torch.float64, device=dev))
     stream = torch.cuda.current_stream()
     n_tiles = ((w + 15) // 16) * ((h + 15) // 16)
 
@@ -215,8 +218,7 @@ def main():
         torch.cuda.synchronize()
         counters = ws.counters()
         sums = out["load_sums"].cpu().numpy()
-        mean_b, std_b = P.load_stats_from_sums(sums[0:2], w * h)
-        mean_i, std_i = P.load_stats_from_sums(sums[2:4], w * h)
+        mean_b, std_b, mean_i, std_i = (float(v) for v in out["load_stats"].cpu().numpy())
         results[name] = dict(
             fps=args.steps / dt, ms_per_frame=1e3 * dt / args.steps, pairs=int(n_pairs),
             sum_blend=int(sums[0]), sum_iter=int(sums[2]),
@@ -441,7 +443,8 @@ def seed_sweep(P, args):
     out = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
                l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
                l_blend=torch.empty((h, w), dtype=torch.int32, device=dev),
-               load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
+               load_sums=torch.zeros(4, dtype=torch.int64, device=dev),
+               load_stats=torch.zeros(4, dtype=torch.float64, device=dev))
     ws = P.Workspace()
     res = []
     for seed in (0, 1, 2):
@@ -504,7 +507,8 @@ def cap_sweep(P, args):
     out = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
                l_iter=torch.empty((h, w), dtype=torch.int32, device=dev),
                l_blend=torch.empty((h, w), dtype=torch.int32, device=dev),
-               load_sums=torch.zeros(4, dtype=torch.int64, device=dev))
+               load_sums=torch.zeros(4, dtype=torch.int64, device=dev),
+               load_stats=torch.zeros(4, dtype=torch.float64, device=dev))
     exact = P.RenderParams(cull=P.ADR_CULL_AABB)
     P.render(sg, cams[0], exact, ws, **out)
     lb = out["l_blend"][out["l_blend"] > 0].double()
@@ -522,7 +526,7 @@ def cap_sweep(P, args):
             P.render(sg, cam, params, ws, **out)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / n_rep
-        _, std_b = P.load_stats_from_sums(out["load_sums"].cpu().numpy()[0:2], w * h)
+        std_b = float(out["load_stats"][1])
         return 1.0 / dt, std_b, out["image"].clamp(0.0, 1.0).clone()
 
     rows = []
@@ -676,7 +680,8 @@ def serve_benchmark(P, args):
     pool = [dict(image=torch.empty((3, hmax, wmax), device="cuda")) for _ in range(n_buf)]
     free = list(range(n_buf))
     cv = threading.Condition()
-    server = P.Server(args.serve_slots)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    server = P.Server(n_slots=args.serve_slots, max_batch=args.serve_batch, memory_budget=budget)
     params = P.RenderParams(cull=P.ADR_CULL_AABB)
     pending, done = [], []
 
@@ -709,7 +714,7 @@ def serve_benchmark(P, args):
             b = free.pop()
         img = pool[b]["image"]
         view = img.view(-1)[: 3 * cam.height * cam.width].view(3, cam.height, cam.width)
-        ticket = server.submit(scenes[sc], cam, params, view)
+        ticket = server.submit(scenes[sc], cam, params, view, arrival_s=arrival)
         with cv:
             pending.append((arrival, ticket, b, sc, cam))
             cv.notify_all()
@@ -717,8 +722,11 @@ def serve_benchmark(P, args):
         pending.append(None)
         cv.notify_all()
     th.join()
+    st = server.stats()
     server.close()
     lat = np.array([(info["done_s"] - arr) * 1e3 for arr, info, _, _ in done if arr - t0 >= warm])
+    batch_sizes = np.array([info["batch_size"] for arr, info, _, _ in done if arr - t0 >= warm])
+    queue_ms = np.array([(info["start_s"] - arr) * 1e3 for arr, info, _, _ in done if arr - t0 >= warm])
     span = max(info["done_s"] for _, info, _, _ in done) - (t0 + warm)
     by_res = {}
     for arr, info, sc, px in done:
@@ -726,6 +734,11 @@ def serve_benchmark(P, args):
             by_res.setdefault(px, []).append((info["done_s"] - arr) * 1e3)
     names = {w * h: f"{w}x{h}" for w, h in res}
     return {"rate_per_s": args.serve_rate, "seconds": args.serve_seconds, "slots": args.serve_slots,
+            "max_batch": args.serve_batch, "memory_budget_bytes": budget,
+            "batches": int(st["batches"]), "largest_batch": int(st["max_batch_seen"]),
+            "mean_frames_per_blend_launch": round(float(batch_sizes.mean()), 3),
+            "reserved_bytes_peak": int(st["reserved_bytes_peak"]), "pool_bytes": int(st["pool_bytes"]),
+            "admission_wait_p99_ms": round(float(np.percentile(queue_ms, 99)), 3),
             "requests": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3), "max_ms": round(float(lat.max()), 3),
             "frames_per_s": round(lat.size / span, 1),

@@ -15,6 +15,10 @@
  *    NULL = the null stream). adr_render waits once per frame, after
  *    Preprocess, for the pair count (the GPU writes it to mapped pinned host
  *    memory); everything else is asynchronous.
+ *  - Device memory for scenes and workspaces comes from an adr_allocator the
+ *    caller may supply (NULL: hipMalloc). Nothing in adr_render or
+ *    adr_render_backward frees device memory with hipFree (which would
+ *    synchronise the whole device).
  *  - Functions return ADR_OK or a negative adr_status; adr_last_error()
  *    returns a thread-local message for the last failure. No C++ exception
  *    crosses this boundary.
@@ -56,9 +60,26 @@ typedef enum {
 typedef struct adr_scene adr_scene;
 
 /* Opaque per-stream scratch (per-Gaussian records, pair and sort buffers,
- * tile ranges). Grows on demand; one workspace must not be used by two
- * renders at the same time. */
+ * tile ranges): four device arenas (per Gaussian, per pair, per tile, and a
+ * few fixed counters), each one allocation. Grows on demand; one workspace
+ * must not be used by two renders at the same time. */
 typedef struct adr_workspace adr_workspace;
+
+/* Caller-supplied device memory (for example a caching allocator).
+ *   alloc(bytes, stream, ctx) returns device memory of the current device,
+ *     at least `bytes` long and 256-byte aligned, usable by work enqueued on
+ *     `stream` (a hipStream_t as void*); NULL on failure (the library then
+ *     returns ADR_E_OOM).
+ *   free(ptr, bytes, stream, ctx) releases a block from alloc. The block may
+ *     still be read or written by work already enqueued on `stream`: the
+ *     allocator must reuse it only for work ordered after that (a
+ *     stream-ordered release, as a caching allocator does).
+ * Both are called on the thread that called into the library. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} adr_allocator;
 
 /* Scene description (Sec. 3.1): centre, covariance as scale and rotation,
  * opacity and SH colour. Arrays are row-major float32, one row per Gaussian:
@@ -68,12 +89,18 @@ typedef struct adr_workspace adr_workspace;
  *   opacity_logits N               opacity = 1 / (1 + exp(-logit))
  *   sh             N x K x 3       real SH coefficients, K = (sh_degree+1)^2,
  *                                  index l*l + l + m (Condon-Shortley phase)
- * The arrays are copied (and transposed to planes) during adr_create_scene;
- * the caller keeps ownership. pointers_on_device = 1: device pointers; 0: host. */
+ * pointers_on_device = 1: device pointers; 0: host.
+ * borrow = 0: the arrays are copied (and transposed to planes) during
+ *   adr_create_scene; the caller keeps ownership of its arrays.
+ * borrow = 1 (device pointers only): no copy. The scene reads the caller's
+ *   arrays in place, in the row-major layout above, for every render; the
+ *   caller keeps them allocated and unchanged until adr_destroy_scene. */
 typedef struct {
   int64_t n;
   int32_t sh_degree; /* 0..3 */
   int32_t pointers_on_device;
+  int32_t borrow;
+  int32_t reserved;  /* 0 */
   const float* means;
   const float* log_scales;
   const float* quats;
@@ -118,7 +145,10 @@ typedef struct {
  *   l_iter        H x W     uint32, entries of the tile list examined (the thread's work)
  *   l_blend       H x W     uint32, Gaussians blended (Eq. 12)
  *   load_sums     4         uint64: sum l_blend, sum l_blend^2, sum l_iter, sum l_iter^2
- *                           over H x W (Eq. 13 follows exactly on the host)
+ *                           over H x W
+ *   load_stats    4         double: mean and population standard deviation of l_blend over
+ *                           the H x W pixels (the load statistic of Eq. 13, zero-load pixels
+ *                           included), then the same of l_iter; from the exact integer sums
  *   tiles_touched N         uint32 per Gaussian (Preprocess)
  *   keys, values  pair_capacity   sorted (tile << 32 | depth bits) keys and Gaussian ids
  *   ranges        2 x T     uint32 [first, last+1) per tile, (0, 0) when empty,
@@ -132,6 +162,7 @@ typedef struct {
   uint32_t* l_iter;
   uint32_t* l_blend;
   uint64_t* load_sums;
+  double* load_stats;
   uint32_t* tiles_touched;
   uint64_t* keys;
   uint32_t* values;
@@ -149,16 +180,40 @@ typedef struct {
   float* d_sh;
 } adr_scene_grads;
 
-/* Creates a scene from desc (see adr_scene_desc). Returns ADR_E_INVALID for
- * n < 0, sh_degree outside 0..3 or NULL arrays with n > 0; ADR_E_OOM when the
- * device copy cannot be allocated. Synchronous. */
-adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** out);
+/* Creates a scene from desc (see adr_scene_desc), the Gaussians of Sec. 3.1.
+ * allocator (may be NULL: hipMalloc/hipFree) provides the device copy and
+ * the staging of host arrays; it must stay valid until adr_destroy_scene.
+ * Returns ADR_E_INVALID for n < 0, sh_degree outside 0..3, NULL arrays with
+ * n > 0, or borrow = 1 with host pointers; ADR_E_OOM when the device copy
+ * cannot be allocated. Synchronous (a borrowed scene enqueues nothing). */
+adr_status adr_create_scene(const adr_scene_desc* desc, const adr_allocator* allocator, adr_scene** out);
 void adr_destroy_scene(adr_scene* scene);
 int64_t adr_scene_size(const adr_scene* scene);
+/* Device bytes the scene holds (0 for a borrowed scene). */
 int64_t adr_scene_bytes(const adr_scene* scene);
 
-adr_status adr_workspace_create(adr_workspace** out);
+/* Creates an empty workspace on the current device. allocator (may be NULL)
+ * provides its arenas and must stay valid until adr_workspace_destroy. With
+ * a caller allocator an arena that is too small for a frame is replaced
+ * inside adr_render (alloc the new one, stream-ordered free of the old one).
+ * With NULL the library allocates with hipMalloc and never calls hipFree
+ * inside a render: a replaced arena is kept until the next
+ * adr_workspace_reserve or adr_workspace_destroy, which free it (and
+ * synchronise the device). ADR_E_OOM if the pinned counters cannot be
+ * allocated. */
+adr_status adr_workspace_create(const adr_allocator* allocator, adr_workspace** out);
+/* Waits for the device, then releases every arena. */
 void adr_workspace_destroy(adr_workspace* ws);
+/* Grows the arenas (never shrinks them) to hold a frame of n_gauss
+ * Gaussians, n_pairs Gaussian-tile pairs and n_tiles tiles, and frees the
+ * arenas kept from earlier growth. Synchronises the device. A render that
+ * stays within the reserved sizes allocates nothing. */
+adr_status adr_workspace_reserve(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles);
+/* Device bytes a workspace needs for such a frame (arena sizes, without
+ * growth headroom); -1 for negative arguments. Host arithmetic only. */
+int64_t adr_workspace_bytes(int64_t n_gauss, int64_t n_pairs, int64_t n_tiles);
+/* Device bytes the workspace's arenas hold now, kept arenas included. */
+int64_t adr_workspace_capacity_bytes(const adr_workspace* ws);
 
 /* Renders one frame: Preprocess (projection, SH colour, cull per params.cull),
  * InclusiveSum, DuplicateWithKeys, SortPairs, IdentifyTileRanges and Render
@@ -215,43 +270,76 @@ int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
  * is never used as an index). Returns the number of entries written. */
 int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n);
 
-/* Serving: resident scenes, concurrent requests.
+/* Serving: resident scenes, continuous batching of render requests.
  *
- * A server owns n_slots render slots, each a host thread with its own HIP
- * stream (default priority) and workspace on the device current at
- * adr_server_create. Requests start in submission order as slots free up, so
- * up to n_slots frames are in flight on the device at once (their kernels
- * overlap); each request's outputs are bitwise those adr_render gives for it
- * alone. Admission: a request waits in the queue while every slot is busy,
- * and a slot's workspace grows to the largest frame it has rendered, so
- * device memory is bounded by n_slots such workspaces plus the resident
- * scenes. The scene, camera, params and frame of a request are copied at
- * submission; the frame's output buffers (caller-owned device memory) and the
- * scene must stay valid until adr_server_wait returns for its ticket. */
+ * A server keeps no scenes of its own: requests name scenes the caller
+ * created (resident in device memory) and caller-owned output buffers.
+ * Requests are admitted in arrival order as render slots and device memory
+ * free up. Admission reserves the request's workspace footprint,
+ * adr_workspace_bytes(N, pairs, tiles), against memory_budget, with pairs
+ * estimated from the last frame of the same scene, resolution and cull mode
+ * (4 N before the first); at least one request is always admitted. An
+ * admitted request runs Preprocess through the tile order (Sec. 3.2, stages
+ * 1-5) on its slot's stream, so the stages of several requests overlap on the
+ * device. Whenever frames are ready, one launch blends all of them: every
+ * (request, tile) item of the batch is a workgroup of that launch, while the
+ * next requests' earlier stages keep running. Each frame's outputs are
+ * bitwise those adr_render gives for the same request alone. Workspace
+ * arenas come from a device pool the server owns (sized blocks kept for
+ * reuse, released at adr_server_destroy); a request returns its arenas to
+ * the pool when its frame is done. */
 typedef struct adr_server adr_server;
 
 typedef struct {
-  int32_t status;  /* adr_status of the render (ADR_OK, or its error; see adr_last_error after the wait) */
-  int64_t n_pairs; /* the frame's Gaussian-tile pair count */
-  double submit_s; /* adr_clock_s() when submitted, when a slot started it, when its stream finished */
-  double start_s;
-  double done_s;
+  int32_t n_slots;       /* requests in flight at once, 1..64 */
+  int32_t max_batch;     /* frames per blend launch, 1..64 */
+  int64_t memory_budget; /* device bytes admitted requests may reserve, > 0 */
+} adr_server_config;
+
+typedef struct {
+  int32_t status;    /* adr_status of the frame (ADR_OK, or its error; see adr_last_error after the wait) */
+  int32_t batch_size; /* frames blended in the same launch as this one */
+  int64_t n_pairs;   /* the frame's Gaussian-tile pair count */
+  int64_t batch_id;  /* index of that launch (0, 1, ...) */
+  int64_t footprint; /* bytes reserved at admission */
+  double arrival_s;  /* adr_clock_s(): as given at submission */
+  double submit_s;   /* when submitted */
+  double start_s;    /* when admitted to a slot */
+  double done_s;     /* when its blend launch was seen finished */
 } adr_request_info;
 
-/* n_slots in 1..64. Returns ADR_E_INVALID otherwise, ADR_E_HIP or ADR_E_OOM
- * when a stream or workspace cannot be created. This build returns
- * ADR_E_UNSUPPORTED for valid arguments: serving is switched off until the
- * cause of a GPU fault seen in its first test is found. */
-adr_status adr_server_create(int32_t n_slots, adr_server** out);
-/* Finishes every queued and running request, then releases the slots. */
+typedef struct {
+  int64_t requests_done;
+  int64_t batches;
+  int32_t max_batch_seen;
+  int32_t reserved1;
+  int64_t reserved_bytes_peak; /* largest sum of admitted footprints */
+  int64_t pool_bytes;          /* device bytes the pool holds */
+} adr_server_stats;
+
+/* Creates a server on the current device: config->n_slots slot threads, each
+ * with a HIP stream (default priority) and a workspace, and one thread that
+ * forms and launches the batched blends on a stream of its own. ADR_E_INVALID
+ * for a NULL or out-of-range config; ADR_E_HIP or ADR_E_OOM if a stream,
+ * event, workspace or staging buffer cannot be created. */
+adr_status adr_server_create(const adr_server_config* config, adr_server** out);
+/* Finishes every queued and running request, then releases the slots and
+ * the pool. */
 void adr_server_destroy(adr_server* server);
-/* Queues one frame; writes its ticket. Argument errors are reported here,
- * before anything is queued. */
+/* Queues one frame; writes its ticket. arrival_s (adr_clock_s() seconds, or
+ * 0 for the time of the call) is when the request is taken to have arrived,
+ * the origin of its latency. Argument errors are reported here, before
+ * anything is queued. The scene, the frame's output buffers and the params'
+ * and camera's values are read when the request runs: the scene and buffers
+ * must stay valid until adr_server_wait returns for the ticket. */
 adr_status adr_server_submit(adr_server* server, const adr_scene* scene, const adr_camera* cam,
-                             const adr_render_params* params, const adr_frame* frame, uint64_t* ticket);
+                             const adr_render_params* params, const adr_frame* frame, double arrival_s,
+                             uint64_t* ticket);
 /* Blocks until the ticket's frame has finished on the device, fills info and
  * retires the ticket. ADR_E_INVALID for an unknown ticket. */
 adr_status adr_server_wait(adr_server* server, uint64_t ticket, adr_request_info* info);
+/* Counters since creation. */
+adr_status adr_server_stats_get(adr_server* server, adr_server_stats* out);
 /* Seconds of the steady clock the server time-stamps requests with. */
 double adr_clock_s(void);
 

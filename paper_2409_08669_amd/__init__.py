@@ -22,5 +22,5 @@ from .binding import (  # noqa: F401
     load,
     render,
     render_frame,
-    load_stats_from_sums,
+    torch_allocator,
 )

@@ -36,9 +36,11 @@ STAGES = ("preprocess", "host_wait", "depth_sort", "inclusive_sum", "duplicate",
 
 EXPORTS = (
     "adr_create_scene", "adr_destroy_scene", "adr_scene_size", "adr_scene_bytes",
-    "adr_workspace_create", "adr_workspace_destroy", "adr_render", "adr_render_backward", "adr_render_backward_load",
+    "adr_workspace_create", "adr_workspace_destroy", "adr_workspace_reserve", "adr_workspace_bytes",
+    "adr_workspace_capacity_bytes", "adr_render", "adr_render_backward", "adr_render_backward_load",
     "adr_workspace_stage_times", "adr_workspace_counters", "adr_last_error", "adr_version",
-    "adr_server_create", "adr_server_destroy", "adr_server_submit", "adr_server_wait", "adr_clock_s",
+    "adr_server_create", "adr_server_destroy", "adr_server_submit", "adr_server_wait", "adr_server_stats_get",
+    "adr_clock_s",
 )
 
 
@@ -50,8 +52,17 @@ class AdrError(RuntimeError):
 
 class adr_scene_desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("sh_degree", ctypes.c_int32), ("pointers_on_device", ctypes.c_int32),
+                ("borrow", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("means", ctypes.c_void_p), ("log_scales", ctypes.c_void_p), ("quats", ctypes.c_void_p),
                 ("opacity_logits", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class adr_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class adr_camera(ctypes.Structure):
@@ -68,7 +79,8 @@ class adr_render_params(ctypes.Structure):
 
 class adr_frame(ctypes.Structure):
     _fields_ = [("image", ctypes.c_void_p), ("final_t", ctypes.c_void_p), ("l_iter", ctypes.c_void_p),
-                ("l_blend", ctypes.c_void_p), ("load_sums", ctypes.c_void_p), ("tiles_touched", ctypes.c_void_p),
+                ("l_blend", ctypes.c_void_p), ("load_sums", ctypes.c_void_p), ("load_stats", ctypes.c_void_p),
+                ("tiles_touched", ctypes.c_void_p),
                 ("keys", ctypes.c_void_p), ("values", ctypes.c_void_p), ("ranges", ctypes.c_void_p),
                 ("pair_capacity", ctypes.c_int64), ("n_pairs", ctypes.c_int64)]
 
@@ -92,7 +104,8 @@ def load(path=None):
         raise ImportError(f"{p} is not built; run `python -m paper_2409_08669_amd.build` (needs hipcc)")
     lib = ctypes.CDLL(str(p))
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
-    lib.adr_create_scene.argtypes = [ctypes.POINTER(adr_scene_desc), ctypes.POINTER(vp)]
+    lib.adr_create_scene.argtypes = [ctypes.POINTER(adr_scene_desc), ctypes.POINTER(adr_allocator),
+                                     ctypes.POINTER(vp)]
     lib.adr_create_scene.restype = i32
     lib.adr_destroy_scene.argtypes = [vp]
     lib.adr_destroy_scene.restype = None
@@ -100,10 +113,16 @@ def load(path=None):
     lib.adr_scene_size.restype = i64
     lib.adr_scene_bytes.argtypes = [vp]
     lib.adr_scene_bytes.restype = i64
-    lib.adr_workspace_create.argtypes = [ctypes.POINTER(vp)]
+    lib.adr_workspace_create.argtypes = [ctypes.POINTER(adr_allocator), ctypes.POINTER(vp)]
     lib.adr_workspace_create.restype = i32
     lib.adr_workspace_destroy.argtypes = [vp]
     lib.adr_workspace_destroy.restype = None
+    lib.adr_workspace_reserve.argtypes = [vp, i64, i64, i64]
+    lib.adr_workspace_reserve.restype = i32
+    lib.adr_workspace_bytes.argtypes = [i64, i64, i64]
+    lib.adr_workspace_bytes.restype = i64
+    lib.adr_workspace_capacity_bytes.argtypes = [vp]
+    lib.adr_workspace_capacity_bytes.restype = i64
     lib.adr_render.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
                                ctypes.POINTER(adr_frame), vp, vp]
     lib.adr_render.restype = i32
@@ -118,15 +137,17 @@ def load(path=None):
     lib.adr_workspace_stage_times.restype = i32
     lib.adr_workspace_counters.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), i32]
     lib.adr_workspace_counters.restype = i32
-    lib.adr_server_create.argtypes = [i32, ctypes.POINTER(vp)]
+    lib.adr_server_create.argtypes = [ctypes.POINTER(adr_server_config), ctypes.POINTER(vp)]
     lib.adr_server_create.restype = i32
     lib.adr_server_destroy.argtypes = [vp]
     lib.adr_server_destroy.restype = None
     lib.adr_server_submit.argtypes = [vp, vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
-                                      ctypes.POINTER(adr_frame), ctypes.POINTER(ctypes.c_uint64)]
+                                      ctypes.POINTER(adr_frame), ctypes.c_double, ctypes.POINTER(ctypes.c_uint64)]
     lib.adr_server_submit.restype = i32
     lib.adr_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(adr_request_info)]
     lib.adr_server_wait.restype = i32
+    lib.adr_server_stats_get.argtypes = [vp, ctypes.POINTER(adr_server_stats)]
+    lib.adr_server_stats_get.restype = i32
     lib.adr_clock_s.argtypes = []
     lib.adr_clock_s.restype = ctypes.c_double
     lib.adr_last_error.argtypes = []
@@ -137,9 +158,20 @@ def load(path=None):
     return lib
 
 
+class adr_server_config(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("memory_budget", ctypes.c_int64)]
+
+
 class adr_request_info(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("submit_s", ctypes.c_double),
-                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+    _fields_ = [("status", ctypes.c_int32), ("batch_size", ctypes.c_int32), ("n_pairs", ctypes.c_int64),
+                ("batch_id", ctypes.c_int64), ("footprint", ctypes.c_int64), ("arrival_s", ctypes.c_double),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+class adr_server_stats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("batches", ctypes.c_int64), ("max_batch_seen", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("reserved_bytes_peak", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_int64)]
 
 
 def last_error() -> str:
@@ -186,11 +218,37 @@ def camera_to_c(cam) -> adr_camera:
     return c
 
 
-class Scene:
-    """Device copy of a Gaussian scene (adr_create_scene). Accepts numpy arrays
-    (host) or torch tensors on the GPU; float32, row-major."""
+def torch_allocator(device=None):
+    """An adr_allocator backed by torch's caching allocator: alloc takes a
+    block for the given stream, free hands it back (torch reuses it only for
+    work ordered after the frame on that stream). Keep the returned object
+    alive as long as anything allocated through it."""
+    import torch
 
-    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree: int):
+    dev = torch.cuda.current_device() if device is None else int(device)
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0)))
+        except Exception:  # reported to the library as a failed allocation (ADR_E_OOM)
+            return None
+
+    def _free(ptr, nbytes, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = adr_allocator()
+    a.alloc, a.free, a.ctx = ALLOC_FN(_alloc), FREE_FN(_free), None
+    return a
+
+
+class Scene:
+    """A Gaussian scene (adr_create_scene). Accepts numpy arrays (host) or
+    torch tensors on the GPU; float32, row-major. borrow=True (GPU tensors
+    only) keeps the caller's tensors and reads them in place; the scene holds
+    references to them."""
+
+    def __init__(self, means, log_scales, quats, opacity_logits, sh, sh_degree: int, borrow: bool = False,
+                 allocator=None):
         lib = load()
         arrays = [means, log_scales, quats, opacity_logits, sh]
         on_device = hasattr(means, "is_cuda") and bool(means.is_cuda)
@@ -209,16 +267,20 @@ class Scene:
         d.n = int(keep[0].shape[0])
         d.sh_degree = int(sh_degree)
         d.pointers_on_device = 1 if on_device else 0
+        d.borrow = 1 if borrow else 0
         d.means, d.log_scales, d.quats, d.opacity_logits, d.sh = ptrs
         h = ctypes.c_void_p()
-        _check(lib.adr_create_scene(ctypes.byref(d), ctypes.byref(h)))
+        self._allocator = allocator
+        _check(lib.adr_create_scene(ctypes.byref(d), ctypes.byref(allocator) if allocator is not None else None,
+                                    ctypes.byref(h)))
         self._h = h
+        self._borrowed = keep if borrow else None  # the arrays a borrowed scene reads
         self.n = d.n
         self.sh_degree = int(sh_degree)
 
     @classmethod
-    def from_synth(cls, s) -> "Scene":
-        return cls(s.means, s.log_scales, s.quats, s.opacity_logits, s.sh, s.sh_degree)
+    def from_synth(cls, s, **kw) -> "Scene":
+        return cls(s.means, s.log_scales, s.quats, s.opacity_logits, s.sh, s.sh_degree, **kw)
 
     @property
     def handle(self):
@@ -232,6 +294,7 @@ class Scene:
         if getattr(self, "_h", None) is not None and self._h.value:
             load().adr_destroy_scene(self._h)
             self._h = ctypes.c_void_p()
+            self._borrowed = None
 
     def __del__(self):
         try:
@@ -241,13 +304,27 @@ class Scene:
 
 
 class Workspace:
-    """adr_workspace: per-stream scratch that grows on demand."""
+    """adr_workspace: per-stream scratch that grows on demand. allocator:
+    None (the library's hipMalloc arenas, kept until reserve() or close() when
+    replaced), "torch" (torch's caching allocator) or an adr_allocator."""
 
-    def __init__(self):
+    def __init__(self, allocator=None):
         lib = load()
+        if allocator == "torch":
+            allocator = torch_allocator()
+        self._allocator = allocator
         h = ctypes.c_void_p()
-        _check(lib.adr_workspace_create(ctypes.byref(h)))
+        _check(lib.adr_workspace_create(ctypes.byref(allocator) if allocator is not None else None,
+                                        ctypes.byref(h)))
         self._h = h
+
+    def reserve(self, n_gauss: int, n_pairs: int, n_tiles: int):
+        """adr_workspace_reserve: grow ahead of time (synchronises the device)."""
+        _check(load().adr_workspace_reserve(self._h, int(n_gauss), int(n_pairs), int(n_tiles)))
+
+    @property
+    def capacity_bytes(self) -> int:
+        return int(load().adr_workspace_capacity_bytes(self._h))
 
     @property
     def handle(self):
@@ -257,6 +334,11 @@ class Workspace:
         buf = (ctypes.c_float * len(STAGES))()
         k = load().adr_workspace_stage_times(self._h, buf, len(STAGES))
         return {STAGES[i]: float(buf[i]) for i in range(k)}
+
+    @staticmethod
+    def bytes_for(n_gauss: int, n_pairs: int, n_tiles: int) -> int:
+        """adr_workspace_bytes: device bytes a frame of this size needs."""
+        return int(load().adr_workspace_bytes(int(n_gauss), int(n_pairs), int(n_tiles)))
 
     def counters(self) -> dict:
         buf = (ctypes.c_int64 * 6)()
@@ -281,7 +363,7 @@ def _ptr(t):
 
 
 def render(scene: Scene, cam, params: RenderParams, ws: Workspace, image, final_t=None, l_iter=None,
-           l_blend=None, load_sums=None, tiles_touched=None, keys=None, values=None, ranges=None,
+           l_blend=None, load_sums=None, load_stats=None, tiles_touched=None, keys=None, values=None, ranges=None,
            pair_capacity: int = 0, stream=None) -> int:
     """adr_render into caller-allocated device tensors; returns the pair count.
     Raises AdrError on any non-OK status (ADR_E_WORKSPACE carries n_pairs)."""
@@ -290,7 +372,7 @@ def render(scene: Scene, cam, params: RenderParams, ws: Workspace, image, final_
     lib = load()
     f = adr_frame()
     f.image, f.final_t, f.l_iter, f.l_blend = _ptr(image), _ptr(final_t), _ptr(l_iter), _ptr(l_blend)
-    f.load_sums, f.tiles_touched = _ptr(load_sums), _ptr(tiles_touched)
+    f.load_sums, f.load_stats, f.tiles_touched = _ptr(load_sums), _ptr(load_stats), _ptr(tiles_touched)
     f.keys, f.values, f.ranges = _ptr(keys), _ptr(values), _ptr(ranges)
     f.pair_capacity = int(pair_capacity)
     c = camera_to_c(cam)
@@ -323,6 +405,7 @@ def render_frame(scene: Scene, cam, params: RenderParams, ws: Workspace = None, 
         l_iter=torch.empty((h, w), dtype=torch.int32, device=device),
         l_blend=torch.empty((h, w), dtype=torch.int32, device=device),
         load_sums=torch.zeros(4, dtype=torch.int64, device=device),
+        load_stats=torch.zeros(4, dtype=torch.float64, device=device),
     )
     extra = {}
     cap = 0
@@ -392,8 +475,9 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, means, log_scales, quats, opacity_logits, sh, cam, params, ws):
+            # zero-copy: the scene reads the tensors in place until backward
             scene = Scene(means.detach(), log_scales.detach(), quats.detach(), opacity_logits.detach(),
-                          sh.detach(), int(round(math.sqrt(sh.shape[1]))) - 1)
+                          sh.detach(), int(round(math.sqrt(sh.shape[1]))) - 1, borrow=True)
             h, w = int(cam.height), int(cam.width)
             dev = means.device
             frame = dict(image=torch.empty((3, h, w), device=dev), final_t=torch.empty((h, w), device=dev),
@@ -425,56 +509,54 @@ def render_differentiable(means, log_scales, quats, opacity_logits, sh, cam, par
 _render_fn = None
 
 
-def load_stats_from_sums(sums, n_pixels: int):
-    """Exact (mean, population std) from the integer sums (sum, sum of squares)
-    that adr_render writes; Eq. 13 over all H x W pixels."""
-    import math
-    s1, s2 = int(sums[0]), int(sums[1])
-    mean = s1 / n_pixels
-    var = (n_pixels * s2 - s1 * s1) / (n_pixels * n_pixels)
-    return mean, math.sqrt(max(var, 0.0))
-
-
 def clock_s() -> float:
     """The steady clock the server time-stamps requests with (seconds)."""
     return float(load().adr_clock_s())
 
 
 class Server:
-    """adr_server: n_slots render slots (host thread + HIP stream + workspace
-    each) consuming queued frame requests over resident scenes."""
+    """adr_server: continuous batching of render requests over resident
+    scenes (n_slots requests in flight, blends of up to max_batch frames per
+    launch, admission against memory_budget device bytes)."""
 
-    def __init__(self, n_slots: int = 4):
+    def __init__(self, n_slots: int = 8, max_batch: int = 16, memory_budget: int = 16 << 30):
+        cfg = adr_server_config()
+        cfg.n_slots, cfg.max_batch, cfg.memory_budget = int(n_slots), int(max_batch), int(memory_budget)
         h = ctypes.c_void_p()
-        _check(load().adr_server_create(int(n_slots), ctypes.byref(h)))
+        _check(load().adr_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._keep = {}  # ticket -> objects that must outlive the request
 
     def submit(self, scene: Scene, cam, params: RenderParams, image, final_t=None, l_iter=None, l_blend=None,
-               load_sums=None) -> int:
+               load_sums=None, load_stats=None, arrival_s: float = 0.0) -> int:
         """Queues one frame into caller-allocated device tensors; returns its
-        ticket. The tensors and the scene must stay alive until wait()."""
+        ticket. arrival_s (clock_s() seconds; 0 = now) is the origin of its
+        latency. The tensors and the scene must stay alive until wait()."""
         f = adr_frame()
         f.image, f.final_t, f.l_iter, f.l_blend = _ptr(image), _ptr(final_t), _ptr(l_iter), _ptr(l_blend)
-        f.load_sums = _ptr(load_sums)
+        f.load_sums, f.load_stats = _ptr(load_sums), _ptr(load_stats)
         c, p = camera_to_c(cam), params.to_c()
         t = ctypes.c_uint64()
         _check(load().adr_server_submit(self._h, scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
-                                        ctypes.byref(t)))
-        self._keep[int(t.value)] = (scene, image, final_t, l_iter, l_blend, load_sums)
+                                        float(arrival_s), ctypes.byref(t)))
+        self._keep[int(t.value)] = (scene, image, final_t, l_iter, l_blend, load_sums, load_stats)
         return int(t.value)
 
     def wait(self, ticket: int) -> dict:
-        """Blocks until the frame is done; returns its status, pair count and
-        time stamps (submit, start, done; seconds of clock_s())."""
+        """Blocks until the frame is done; returns its status, pair count,
+        batch, footprint and time stamps (clock_s() seconds)."""
         info = adr_request_info()
         _check(load().adr_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(info)))
         self._keep.pop(int(ticket), None)
-        out = dict(status=int(info.status), n_pairs=int(info.n_pairs), submit_s=info.submit_s,
-                   start_s=info.start_s, done_s=info.done_s)
+        out = {k: getattr(info, k) for k, _ in adr_request_info._fields_}
         if info.status != ADR_OK:
             raise AdrError(int(info.status), last_error())
         return out
+
+    def stats(self) -> dict:
+        st = adr_server_stats()
+        _check(load().adr_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in adr_server_stats._fields_ if not k.startswith("reserved1")}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/adr.h"
 
@@ -17,17 +18,59 @@ constexpr int kQuad = 8;      // each wave of a tile's workgroup owns an 8 x 8 q
 constexpr int kWave = 64;     // CDNA wavefront
 
 // ---------------------------------------------------------------------------
-// Scene in device memory (structure of arrays, coalesced per Gaussian index)
+// Scene in device memory
 // ---------------------------------------------------------------------------
+// An owned scene is a structure of arrays, coalesced per Gaussian index: three
+// float4 planes and 3K SH planes. A borrowed scene is the caller's row-major
+// arrays, read in place.
 struct DeviceScene {
   int64_t n = 0;
   int32_t sh_degree = 0;
   int32_t n_coeff = 1;       // (degree+1)^2
+  bool borrowed = false;
+  // owned layout
   float4* geo_a = nullptr;   // (mean.x, mean.y, mean.z, opacity logit)
   float4* geo_b = nullptr;   // (log_scale.x, .y, .z, 0)
   float4* geo_q = nullptr;   // quaternion (w, x, y, z), as given
   float* sh = nullptr;       // planes [3*K][n]: plane (k*3 + channel)
+  // borrowed layout (adr_scene_desc's arrays)
+  const float* means = nullptr;
+  const float* log_scales = nullptr;
+  const float* quats = nullptr;
+  const float* logits = nullptr;
+  const float* sh_rows = nullptr;  // N x K x 3
   size_t bytes = 0;
+};
+
+// Device reads of one Gaussian's inputs, for either scene layout. Entry i of
+// the SH coefficients is coefficient i / 3, channel i % 3.
+struct PlanarScene {
+  const float4* __restrict__ geo_a;
+  const float4* __restrict__ geo_b;
+  const float4* __restrict__ geo_q;
+  const float* __restrict__ sh;
+  int64_t n;
+  __device__ float4 a(int64_t g) const { return geo_a[g]; }
+  __device__ float4 b(int64_t g) const { return geo_b[g]; }
+  __device__ float4 q(int64_t g) const { return geo_q[g]; }
+  __device__ float coef(int i, int64_t g) const { return sh[(int64_t)i * n + g]; }
+};
+
+struct RowMajorScene {
+  const float* __restrict__ means;
+  const float* __restrict__ log_scales;
+  const float* __restrict__ quats;
+  const float* __restrict__ logits;
+  const float* __restrict__ sh;
+  int32_t per;  // 3K floats per Gaussian
+  __device__ float4 a(int64_t g) const {
+    return make_float4(means[3 * g], means[3 * g + 1], means[3 * g + 2], logits[g]);
+  }
+  __device__ float4 b(int64_t g) const {
+    return make_float4(log_scales[3 * g], log_scales[3 * g + 1], log_scales[3 * g + 2], 0.f);
+  }
+  __device__ float4 q(int64_t g) const { return *reinterpret_cast<const float4*>(quats + 4 * g); }
+  __device__ float coef(int i, int64_t g) const { return sh[g * per + i]; }
 };
 
 // ---------------------------------------------------------------------------
@@ -100,7 +143,19 @@ struct BlendArgs {
 struct SortBuffers {
   uint32_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
-  int64_t capacity = 0;
+};
+
+// One device allocation carved into a workspace's arrays.
+struct Arena {
+  uint8_t* base = nullptr;
+  size_t bytes = 0;
+};
+
+// How a workspace gets memory when a frame needs more than it holds.
+enum class Growth {
+  kAllocator,  // the caller's adr_allocator: alloc the new arena, stream-ordered free of the old
+  kDefault,    // hipMalloc; the old arena is kept until reserve/destroy (no hipFree in a render)
+  kNone,       // fixed memory (the no-allocation entry point): too small is an error
 };
 
 }  // namespace adr
@@ -108,11 +163,18 @@ struct SortBuffers {
 struct adr_scene {
   adr::DeviceScene d;
   uint64_t uid = 0;  // unique per created scene in this process (a freed scene's address may be reused)
+  adr_allocator alloc{};  // provider of the owned copy (alloc == NULL: hipMalloc)
 };
 
 struct adr_workspace {
-  // per Gaussian
-  int64_t gauss_capacity = 0;
+  adr::Growth growth = adr::Growth::kDefault;
+  bool headroom = true;  // grow arenas 25% past the frame's need
+  adr_allocator alloc{};
+  adr::Arena gauss_arena, pair_arena, tile_arena, fixed_arena, grad_arena;
+  std::vector<adr::Arena> retired;  // kDefault: arenas replaced during renders, freed at reserve/destroy
+  // capacities the arenas are carved for
+  int64_t gauss_capacity = 0, pair_capacity = 0, tile_capacity = 0, grad_capacity = 0;
+  // per Gaussian (gauss arena)
   adr::RenderRecord* rec = nullptr;
   adr::ExactRecord* exact = nullptr;
   uint2* tile_rect = nullptr;      // (tx_lo | tx_hi << 16, ty_lo | ty_hi << 16)
@@ -121,32 +183,30 @@ struct adr_workspace {
   uint32_t* touched_sorted = nullptr;  // tiles_touched in depth order
   adr::SortBuffers depth;          // (depth key, id) of every Gaussian, sorted by depth
   uint32_t* scan_partials = nullptr;
-  int64_t scan_partials_capacity = 0;
+  ulonglong4* block_parts = nullptr;  // per Preprocess workgroup: pairs, visible, depth-key min, max
+  uint32_t* depth_scratch = nullptr;  // radix digit counts of the depth sort
+  // per pair (pair arena)
+  adr::SortBuffers pairs;          // (tile id, Gaussian id), sorted by tile
   // per DuplicateWithKeys workgroup (kDupPairs pairs): the depth-order index
   // of the Gaussian that holds its first pair, written by the InclusiveSum
   uint32_t* dup_first = nullptr;
-  int64_t dup_first_capacity = 0;
-  ulonglong4* block_parts = nullptr;  // per Preprocess workgroup: pairs, visible, depth-key min, max
-  int64_t block_parts_capacity = 0;
-  // per pair
-  adr::SortBuffers pairs;          // (tile id, Gaussian id), sorted by tile
-  uint32_t* sort_scratch = nullptr;
-  int64_t sort_scratch_capacity = 0;
-  // per tile
+  uint32_t* pair_scratch = nullptr;   // radix digit counts of the tile sort
+  // per tile (tile arena)
   uint32_t* ranges = nullptr;      // 2 * tiles
-  int64_t ranges_capacity = 0;
   uint32_t* tile_order = nullptr;  // render order of the tiles, longest lists first
-  int64_t tile_order_capacity = 0;
   uint32_t* order_counts = nullptr;  // per-block bucket counts of the tile order
-  int64_t order_counts_capacity = 0;
-  // per frame: counters and the two sort histograms, zeroed (with the tile
-  // ranges and the caller's load sums) by one kernel at the start of the frame
+  unsigned long long* wave_sums = nullptr;     // 4 x u64 per render wave (load-sum partials)
+  // fixed arena: counters and the two sort digit totals, and the frame's load
+  // accumulators; cleared at the start of every frame
   unsigned long long* dev_counters = nullptr;  // kCounterSlots u64, see below
   uint32_t* hists = nullptr;                   // 2 x kHistWords: depth sort, tile sort
-  unsigned long long* wave_sums = nullptr;     // 4 x u64 per render wave (load-sum partials)
-  int64_t wave_sums_capacity = 0;
+  unsigned long long* load_acc = nullptr;      // kLoadAccWords: four sums, a block ticket
+  unsigned long long* notify_slot = nullptr;   // kNotifySlots device words (when notify_host is NULL)
+  // gradients (grad arena)
+  float* grad2d = nullptr;              // kGrad2d floats per Gaussian
   unsigned long long* host_counters = nullptr; // pinned copy for adr_workspace_counters
-  // mapped pinned memory the Preprocess kernel writes the pair count into
+  // mapped pinned memory the kernel after Preprocess writes the pair count
+  // into; NULL: it writes notify_slot, which the host copies back
   unsigned long long* notify_host = nullptr;
   unsigned long long* notify_dev = nullptr;
   unsigned long long frame_seq = 0;
@@ -162,8 +222,6 @@ struct adr_workspace {
   adr_camera last_cam{};
   adr_render_params last_params{};
   const uint32_t* last_vals = nullptr;  // its sorted Gaussian ids
-  float* grad2d = nullptr;              // kGrad2d floats per Gaussian
-  int64_t grad2d_capacity = 0;
 };
 
 namespace adr {
@@ -179,6 +237,41 @@ constexpr int kCntBadIndex = 6;    // sort values or positions out of range (0 u
 constexpr int kNotifySlots = 8;    // mapped words: pairs, visible, frame number, depth min, depth max
 constexpr int kCounterSlots = 8;
 constexpr int kHistWords = 4 * 256;  // digit histograms of up to four 8-bit passes
+constexpr int kLoadAccWords = 8;     // sum l_blend, sum l_blend^2, sum l_iter, sum l_iter^2, ticket, unused
+
+// Arena layouts. Each carves an arena at base for the given capacity and,
+// when ws is given, points the workspace's arrays into it; base == nullptr
+// only sizes it. Returns the arena's bytes (every array 256-byte aligned).
+size_t carve_gauss_arena(uint8_t* base, int64_t n, adr_workspace* ws);
+size_t carve_pair_arena(uint8_t* base, int64_t n_pairs, adr_workspace* ws);
+size_t carve_tile_arena(uint8_t* base, int64_t n_tiles, adr_workspace* ws);
+size_t carve_fixed_arena(uint8_t* base, adr_workspace* ws);
+
+// The stages of one frame, split where the serving path batches the blend
+// of several frames: prepare runs Preprocess through the tile order (one
+// host wait for the pair count), finish runs the blend, the load sums and
+// the optional copies. adr_render is prepare + finish.
+struct FramePlan {
+  CamArgs cam;
+  CullArgs cull;
+  BlendArgs blend;
+  int64_t n_tiles = 0;
+  int64_t n_pairs = 0;
+  const uint32_t* tiles = nullptr;  // sorted tile ids of the pairs
+  const uint32_t* vals = nullptr;   // sorted Gaussian ids of the pairs
+  bool want_load = false;           // load sums or statistics requested
+};
+adr_status render_prepare(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                          adr_frame* out, adr_workspace* ws, hipStream_t stream, FramePlan& plan);
+adr_status render_finish(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                         adr_frame* out, adr_workspace* ws, hipStream_t stream, const FramePlan& plan,
+                         bool blend_launched);
+// Returns the per-Gaussian, per-pair and per-tile arenas to the allocator
+// (nothing may use them any more); the next frame acquires them again.
+void workspace_release_frame_arenas(adr_workspace* ws);
+// Grows ws's arenas for a frame (nothing is enqueued); ADR_E_WORKSPACE for
+// a fixed-memory workspace that is too small.
+adr_status ensure_capacity(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles, hipStream_t stream);
 
 // Thread-local error message for adr_last_error.
 void set_error(const std::string& msg);
@@ -197,16 +290,17 @@ adr_status hip_fail(hipError_t e, const char* what);
 hipError_t launch_pack_scene(const adr_scene_desc& desc, const float* means, const float* log_scales,
                              const float* quats, const float* logits, const float* sh, DeviceScene& d,
                              hipStream_t stream);
-hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_sums, hipStream_t stream);
+hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, hipStream_t stream);
 int64_t preprocess_blocks(int64_t n);
 // Frames whose tile ranges have at most this many words have them cleared
 // (with the counters and the load sums) by the kernel that follows
 // Preprocess instead of a launch of their own.
 constexpr int64_t kNotifyClearMax = (int64_t)1 << 17;
-// n_ranges, load_sums: what the frame-init launch clears, cleared here when
+// n_ranges: what the frame-init launch clears (the tile ranges, with the
+// counters and load accumulators) is cleared here when
 // 0 < n_ranges <= kNotifyClearMax (n_ranges = 0: nothing is cleared)
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
-                             int64_t n_ranges, uint64_t* load_sums, hipStream_t stream);
+                             int64_t n_ranges, hipStream_t stream);
 hipError_t launch_inclusive_sum(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* partials,
                                 uint32_t* dup_first, hipStream_t stream);
 int64_t inclusive_sum_partials(int64_t n);
@@ -229,9 +323,39 @@ hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tile
                              hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
                          const uint32_t* ranges, const uint32_t* order, int64_t n_pairs, int64_t n_gauss,
-                         const CamArgs& cam, const BlendArgs& blend, adr_frame* out, adr_workspace* ws,
-                         hipStream_t stream);
-hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums, hipStream_t stream);
+                         const CamArgs& cam, const BlendArgs& blend, const adr_frame* out, bool want_load,
+                         adr_workspace* ws, hipStream_t stream);
+// One frame's blend in a batched launch (the serving path): its buffers,
+// camera and blend arguments, and its workgroups [block_base,
+// block_base + n_tiles) of the launch.
+struct BlendJob {
+  const RenderRecord* rec;
+  const ExactRecord* exact;
+  const uint32_t* vals;
+  const uint32_t* ranges;
+  const uint32_t* order;
+  float* image;
+  float* final_t;
+  uint32_t* l_iter;
+  uint32_t* l_blend;
+  ulonglong4* wave_sums;
+  unsigned long long* counters;
+  uint32_t n_pairs, n_gauss;
+  int32_t n_tiles, block_base;
+  CamArgs cam;
+  BlendArgs blend;
+};
+BlendJob make_blend_job(const adr_workspace* ws, const RenderRecord* rec, const ExactRecord* exact,
+                        const uint32_t* vals, const CamArgs& cam, const BlendArgs& blend, int64_t n_pairs,
+                        int64_t n_gauss, const adr_frame* out, bool want_load);
+// jobs_dev: n_jobs jobs in device memory, ascending block_base, covering
+// [0, total_blocks); any_cap: some job has a load-balancing cap
+hipError_t launch_render_batch(const BlendJob* jobs_dev, int n_jobs, int64_t total_blocks, bool any_cap,
+                               hipStream_t stream);
+// Reduces the render waves' load partials into ws->load_acc; the last
+// workgroup writes the caller's load_sums and load_stats (either may be NULL).
+hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, int64_t n_pixels, uint64_t* load_sums,
+                            double* load_stats, hipStream_t stream);
 // Backward (gradients). Screen-space gradients per Gaussian, kGrad2d floats:
 // d/dx, d/dy, d/d conic (A, B, C), d/d opacity, d/d colour (r, g, b), unused.
 constexpr int kGrad2d = 10;

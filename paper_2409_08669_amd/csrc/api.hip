@@ -1,5 +1,12 @@
 // C ABI: workspace management and the per-frame orchestration of the six
 // stages of Sec. 3.2 on the caller's stream.
+//
+// A workspace is four device arenas (per Gaussian, per pair, per tile, and a
+// few fixed words), each one allocation carved into 256-byte aligned arrays.
+// When a frame needs a larger arena the new one is allocated before the old
+// one is released: through the caller's allocator (a stream-ordered release),
+// or with hipMalloc while the old arena is kept until the next reserve or
+// destroy. No hipFree runs inside a render.
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -25,67 +32,168 @@ adr_status hip_fail(hipError_t e, const char* what) {
 
 namespace {
 
-template <typename T>
-adr_status grow(T*& p, int64_t& cap, int64_t need, const char* what) {
-  if (need <= cap && p) return ADR_OK;
-  int64_t n = need < 1 ? 1 : need;
-  n = n + n / 4;  // headroom so that frame-to-frame jitter does not reallocate
-  if (p) (void)hipFree(p);
-  p = nullptr;
-  cap = 0;
-  if (hipMalloc(&p, (size_t)n * sizeof(T)) != hipSuccess) {
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Carves consecutive 256-byte aligned arrays out of one arena (or only adds
+// up their sizes when base is null).
+struct Carver {
+  uint8_t* base;
+  size_t off = 0;
+  template <class T>
+  T* take(int64_t count) {
+    off = align256(off);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)(count > 0 ? count : 0) * sizeof(T);
+    return p;
+  }
+  size_t bytes() const { return align256(off); }
+};
+
+}  // namespace
+
+size_t carve_gauss_arena(uint8_t* base, int64_t n, adr_workspace* ws) {
+  Carver c{base};
+  auto* rec = c.take<RenderRecord>(n);
+  auto* exact = c.take<ExactRecord>(n);
+  auto* rect = c.take<uint2>(n);
+  auto* touched = c.take<uint32_t>(n);
+  auto* offsets = c.take<uint32_t>(n);
+  auto* touched_sorted = c.take<uint32_t>(n);
+  auto* dk0 = c.take<uint32_t>(n);
+  auto* dk1 = c.take<uint32_t>(n);
+  auto* dv0 = c.take<uint32_t>(n);
+  auto* dv1 = c.take<uint32_t>(n);
+  auto* scan_partials = c.take<uint32_t>(inclusive_sum_partials(n) + 1);
+  auto* block_parts = c.take<ulonglong4>(preprocess_blocks(n));
+  auto* scratch = c.take<uint32_t>(sort_scratch_entries(n));
+  if (ws) {
+    ws->rec = rec;
+    ws->exact = exact;
+    ws->tile_rect = rect;
+    ws->touched = touched;
+    ws->offsets = offsets;
+    ws->touched_sorted = touched_sorted;
+    ws->depth.keys[0] = dk0;
+    ws->depth.keys[1] = dk1;
+    ws->depth.vals[0] = dv0;
+    ws->depth.vals[1] = dv1;
+    ws->scan_partials = scan_partials;
+    ws->block_parts = block_parts;
+    ws->depth_scratch = scratch;
+  }
+  return c.bytes();
+}
+
+size_t carve_pair_arena(uint8_t* base, int64_t n_pairs, adr_workspace* ws) {
+  Carver c{base};
+  auto* k0 = c.take<uint32_t>(n_pairs);
+  auto* k1 = c.take<uint32_t>(n_pairs);
+  auto* v0 = c.take<uint32_t>(n_pairs);
+  auto* v1 = c.take<uint32_t>(n_pairs);
+  auto* dup_first = c.take<uint32_t>(duplicate_blocks(n_pairs) + 1);
+  auto* scratch = c.take<uint32_t>(sort_scratch_entries(n_pairs));
+  if (ws) {
+    ws->pairs.keys[0] = k0;
+    ws->pairs.keys[1] = k1;
+    ws->pairs.vals[0] = v0;
+    ws->pairs.vals[1] = v1;
+    ws->dup_first = dup_first;
+    ws->pair_scratch = scratch;
+  }
+  return c.bytes();
+}
+
+size_t carve_tile_arena(uint8_t* base, int64_t n_tiles, adr_workspace* ws) {
+  Carver c{base};
+  auto* ranges = c.take<uint32_t>(2 * n_tiles);
+  auto* order = c.take<uint32_t>(n_tiles);
+  auto* counts = c.take<uint32_t>(tile_order_scratch((int)n_tiles));
+  auto* wave_sums = c.take<unsigned long long>(16 * n_tiles);  // 4 waves x 4 sums per tile
+  if (ws) {
+    ws->ranges = ranges;
+    ws->tile_order = order;
+    ws->order_counts = counts;
+    ws->wave_sums = wave_sums;
+  }
+  return c.bytes();
+}
+
+size_t carve_fixed_arena(uint8_t* base, adr_workspace* ws) {
+  Carver c{base};
+  auto* counters = c.take<unsigned long long>(kCounterSlots);
+  auto* hists = c.take<uint32_t>(2 * kHistWords);
+  auto* load_acc = c.take<unsigned long long>(kLoadAccWords);
+  auto* notify = c.take<unsigned long long>(kNotifySlots);
+  if (ws) {
+    ws->dev_counters = counters;
+    ws->hists = hists;
+    ws->load_acc = load_acc;
+    ws->notify_slot = notify;
+  }
+  return c.bytes();
+}
+
+namespace {
+
+size_t carve_grad_arena(uint8_t* base, int64_t n, adr_workspace* ws) {
+  Carver c{base};
+  auto* g = c.take<float>((int64_t)kGrad2d * n);
+  if (ws) ws->grad2d = g;
+  return c.bytes();
+}
+
+void* acquire(adr_workspace* ws, size_t bytes, hipStream_t stream) {
+  if (ws->growth == Growth::kAllocator) return ws->alloc.alloc(bytes, (void*)stream, ws->alloc.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+// in_render: called while a frame may still use the arena on `stream`
+void release(adr_workspace* ws, Arena& a, hipStream_t stream, bool in_render) {
+  if (!a.base) return;
+  if (ws->growth == Growth::kAllocator) {
+    ws->alloc.free(a.base, a.bytes, (void*)stream, ws->alloc.ctx);
+  } else if (ws->growth == Growth::kDefault) {
+    if (in_render)
+      ws->retired.push_back(a);
+    else
+      (void)hipFree(a.base);
+  }
+  a = Arena{};
+}
+
+void free_retired(adr_workspace* ws) {
+  for (Arena& a : ws->retired) (void)hipFree(a.base);
+  ws->retired.clear();
+}
+
+using CarveFn = size_t (*)(uint8_t*, int64_t, adr_workspace*);
+
+adr_status grow_arena(adr_workspace* ws, Arena& arena, int64_t& cap, int64_t need, CarveFn carve, bool headroom,
+                      bool in_render, hipStream_t stream, const char* what) {
+  if (need <= cap && arena.base) return ADR_OK;
+  if (ws->growth == Growth::kNone) {
+    set_error(std::string("workspace of fixed size too small for the frame's ") + what);
+    return ADR_E_WORKSPACE;
+  }
+  int64_t n = need < 1 ? 1 : need;
+  if (headroom) n += n / 4;  // frame-to-frame jitter does not regrow
+  const size_t bytes = carve(nullptr, n, nullptr);
+  auto* p = static_cast<uint8_t*>(acquire(ws, bytes, stream));
+  if (!p) {
     set_error(std::string("workspace allocation failed: ") + what);
     return ADR_E_OOM;
   }
+  release(ws, arena, stream, in_render);
+  arena.base = p;
+  arena.bytes = bytes;
   cap = n;
+  carve(p, n, ws);
   return ADR_OK;
-}
-
-adr_status ensure_sort_buffers(SortBuffers& sb, int64_t n, const char* what) {
-  if (n <= sb.capacity && sb.keys[0]) return ADR_OK;
-  int64_t c[4] = {sb.capacity, sb.capacity, sb.capacity, sb.capacity};
-  adr_status st;
-  if ((st = grow(sb.keys[0], c[0], n, what)) != ADR_OK) return st;
-  if ((st = grow(sb.keys[1], c[1], n, what)) != ADR_OK) return st;
-  if ((st = grow(sb.vals[0], c[2], n, what)) != ADR_OK) return st;
-  if ((st = grow(sb.vals[1], c[3], n, what)) != ADR_OK) return st;
-  int64_t m = c[0];
-  for (int i = 1; i < 4; ++i) m = c[i] < m ? c[i] : m;
-  sb.capacity = m;
-  return ADR_OK;
-}
-
-adr_status ensure_gauss(adr_workspace* ws, int64_t n) {
-  adr_status st;
-  if (n > ws->gauss_capacity || !ws->rec) {
-    int64_t c[4] = {ws->gauss_capacity, ws->gauss_capacity, ws->gauss_capacity, ws->gauss_capacity};
-    int64_t c5 = ws->gauss_capacity;
-    if ((st = grow(ws->rec, c[0], n, "records")) != ADR_OK) return st;
-    if ((st = grow(ws->exact, c[1], n, "exact records")) != ADR_OK) return st;
-    if ((st = grow(ws->tile_rect, c[2], n, "tile rects")) != ADR_OK) return st;
-    if ((st = grow(ws->touched, c[3], n, "tiles_touched")) != ADR_OK) return st;
-    if ((st = grow(ws->offsets, c5, n, "offsets")) != ADR_OK) return st;
-    int64_t c6 = ws->gauss_capacity;
-    if ((st = grow(ws->touched_sorted, c6, n, "tiles_touched in depth order")) != ADR_OK) return st;
-    int64_t m = c5 < c6 ? c5 : c6;
-    for (int i = 0; i < 4; ++i) m = c[i] < m ? c[i] : m;
-    ws->gauss_capacity = m;
-  }
-  if ((st = ensure_sort_buffers(ws->depth, n, "depth sort")) != ADR_OK) return st;
-  if ((st = grow(ws->sort_scratch, ws->sort_scratch_capacity, sort_scratch_entries(n), "sort scratch")) != ADR_OK)
-    return st;
-  if ((st = grow(ws->block_parts, ws->block_parts_capacity, preprocess_blocks(n), "preprocess partials")) != ADR_OK)
-    return st;
-  return grow(ws->scan_partials, ws->scan_partials_capacity, inclusive_sum_partials(n) + 1, "scan partials");
-}
-
-adr_status ensure_pairs(adr_workspace* ws, int64_t p) {
-  adr_status st;
-  if ((st = ensure_sort_buffers(ws->pairs, p, "pair sort")) != ADR_OK) return st;
-  if ((st = grow(ws->dup_first, ws->dup_first_capacity, duplicate_blocks(p) + 1, "pair chunk starts")) != ADR_OK)
-    return st;
-  return grow(ws->sort_scratch, ws->sort_scratch_capacity, sort_scratch_entries(p), "sort scratch");
 }
 
 int bits_for(int64_t v) {
@@ -95,39 +203,65 @@ int bits_for(int64_t v) {
 }
 
 }  // namespace
+
+adr_status ensure_capacity(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles, hipStream_t stream) {
+  adr_status st;
+  const bool h = ws->headroom;
+  if ((st = grow_arena(ws, ws->gauss_arena, ws->gauss_capacity, n_gauss, carve_gauss_arena, h, true, stream,
+                       "Gaussians")) != ADR_OK)
+    return st;
+  if ((st = grow_arena(ws, ws->pair_arena, ws->pair_capacity, n_pairs, carve_pair_arena, h, true, stream,
+                       "pairs")) != ADR_OK)
+    return st;
+  return grow_arena(ws, ws->tile_arena, ws->tile_capacity, n_tiles, carve_tile_arena, h, true, stream, "tiles");
+}
+
+void workspace_release_frame_arenas(adr_workspace* ws) {
+  release(ws, ws->gauss_arena, nullptr, false);
+  release(ws, ws->pair_arena, nullptr, false);
+  release(ws, ws->tile_arena, nullptr, false);
+  ws->gauss_capacity = ws->pair_capacity = ws->tile_capacity = 0;
+}
+
 }  // namespace adr
 
 using namespace adr;
 
-static void free_workspace_buffers(adr_workspace* ws) {
-  void* bufs[] = {ws->rec, ws->exact, ws->tile_rect, ws->touched, ws->offsets, ws->touched_sorted, ws->depth.keys[0],
-                  ws->depth.keys[1], ws->depth.vals[0], ws->depth.vals[1], ws->scan_partials, ws->pairs.keys[0],
-                  ws->pairs.keys[1], ws->pairs.vals[0], ws->pairs.vals[1], ws->dup_first, ws->sort_scratch, ws->ranges,
-                  ws->tile_order, ws->order_counts, ws->wave_sums, ws->dev_counters, ws->hists, ws->block_parts};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+static void free_workspace(adr_workspace* ws) {
+  Arena* arenas[] = {&ws->gauss_arena, &ws->pair_arena, &ws->tile_arena, &ws->fixed_arena, &ws->grad_arena};
+  for (Arena* a : arenas) release(ws, *a, nullptr, false);
+  free_retired(ws);
   if (ws->host_counters) (void)hipHostFree(ws->host_counters);
   if (ws->notify_host) (void)hipHostFree(ws->notify_host);
+  for (auto& e : ws->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ws;
 }
 
 extern "C" const char* adr_last_error(void) { return g_error.c_str(); }
 
-extern "C" const char* adr_version(void) { return "adr-gfx950 0.1"; }
+extern "C" const char* adr_version(void) { return "adr-gfx950 0.2"; }
 
-extern "C" adr_status adr_workspace_create(adr_workspace** out) {
+extern "C" adr_status adr_workspace_create(const adr_allocator* allocator, adr_workspace** out) {
   if (!out) {
     set_error("adr_workspace_create: NULL argument");
     return ADR_E_INVALID;
   }
   *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free)) {
+    set_error("adr_workspace_create: an allocator needs both alloc and free");
+    return ADR_E_INVALID;
+  }
   adr_workspace* ws = new (std::nothrow) adr_workspace();
   if (!ws) {
     set_error("adr_workspace_create: host allocation failed");
     return ADR_E_OOM;
   }
-  bool ok = hipMalloc(&ws->dev_counters, kCounterSlots * sizeof(unsigned long long)) == hipSuccess &&
-            hipMalloc(&ws->hists, 2 * kHistWords * sizeof(uint32_t)) == hipSuccess &&
-            hipHostMalloc(&ws->host_counters, kCounterSlots * sizeof(unsigned long long), hipHostMallocDefault) ==
+  if (allocator) {
+    ws->growth = Growth::kAllocator;
+    ws->alloc = *allocator;
+  }
+  bool ok = hipHostMalloc(&ws->host_counters, kCounterSlots * sizeof(unsigned long long), hipHostMallocDefault) ==
                 hipSuccess &&
             hipHostMalloc(&ws->notify_host, kNotifySlots * sizeof(unsigned long long),
                           hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess;
@@ -136,20 +270,27 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
     std::memset(ws->notify_host, 0, kNotifySlots * sizeof(unsigned long long));
     ok = hipHostGetDevicePointer((void**)&ws->notify_dev, ws->notify_host, 0) == hipSuccess;
   }
+  if (ok) {
+    const size_t bytes = carve_fixed_arena(nullptr, nullptr);
+    auto* p = static_cast<uint8_t*>(acquire(ws, bytes, nullptr));
+    ok = p != nullptr;
+    if (ok) {
+      ws->fixed_arena = Arena{p, bytes};
+      carve_fixed_arena(p, ws);
+    }
+  }
   if (!ok) {
     (void)hipGetLastError();
-    free_workspace_buffers(ws);
-    delete ws;
+    free_workspace(ws);
     set_error("adr_workspace_create: allocation failed");
     return ADR_E_OOM;
   }
   for (int i = 0; i < adr_workspace::kEvents; ++i) {
     if (hipEventCreate(&ws->ev[i]) != hipSuccess) {
       (void)hipGetLastError();
+      ws->ev[i] = nullptr;
+      free_workspace(ws);
       set_error("adr_workspace_create: hipEventCreate failed");
-      for (int k = 0; k < i; ++k) (void)hipEventDestroy(ws->ev[k]);
-      free_workspace_buffers(ws);
-      delete ws;
       return ADR_E_HIP;
     }
   }
@@ -160,10 +301,42 @@ extern "C" adr_status adr_workspace_create(adr_workspace** out) {
 extern "C" void adr_workspace_destroy(adr_workspace* ws) {
   if (!ws) return;
   (void)hipDeviceSynchronize();
-  free_workspace_buffers(ws);
-  for (auto& e : ws->ev)
-    if (e) (void)hipEventDestroy(e);
-  delete ws;
+  free_workspace(ws);
+}
+
+extern "C" int64_t adr_workspace_bytes(int64_t n_gauss, int64_t n_pairs, int64_t n_tiles) {
+  if (n_gauss < 0 || n_pairs < 0 || n_tiles < 0) return -1;
+  return (int64_t)(carve_gauss_arena(nullptr, n_gauss, nullptr) + carve_pair_arena(nullptr, n_pairs, nullptr) +
+                   carve_tile_arena(nullptr, n_tiles, nullptr) + carve_fixed_arena(nullptr, nullptr));
+}
+
+extern "C" int64_t adr_workspace_capacity_bytes(const adr_workspace* ws) {
+  if (!ws) return -1;
+  size_t b = ws->gauss_arena.bytes + ws->pair_arena.bytes + ws->tile_arena.bytes + ws->fixed_arena.bytes +
+             ws->grad_arena.bytes;
+  for (const Arena& a : ws->retired) b += a.bytes;
+  return (int64_t)b;
+}
+
+extern "C" adr_status adr_workspace_reserve(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles) {
+  if (!ws || n_gauss < 0 || n_pairs < 0 || n_tiles < 0) {
+    set_error("adr_workspace_reserve: NULL workspace or negative size");
+    return ADR_E_INVALID;
+  }
+  if (ws->growth == Growth::kNone) {
+    set_error("adr_workspace_reserve: fixed-size workspace");
+    return ADR_E_INVALID;
+  }
+  if (hipDeviceSynchronize() != hipSuccess) return hip_fail(hipGetLastError(), "adr_workspace_reserve");
+  free_retired(ws);
+  adr_status st;
+  if ((st = grow_arena(ws, ws->gauss_arena, ws->gauss_capacity, n_gauss, carve_gauss_arena, false, false, nullptr,
+                       "Gaussians")) != ADR_OK)
+    return st;
+  if ((st = grow_arena(ws, ws->pair_arena, ws->pair_capacity, n_pairs, carve_pair_arena, false, false, nullptr,
+                       "pairs")) != ADR_OK)
+    return st;
+  return grow_arena(ws, ws->tile_arena, ws->tile_capacity, n_tiles, carve_tile_arena, false, false, nullptr, "tiles");
 }
 
 namespace adr {
@@ -264,54 +437,11 @@ BlendArgs blend_args(const adr_render_params* p) {
   return bl;
 }
 
-}  // namespace
-
-extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
-                                 adr_frame* out, adr_workspace* ws, void* stream_ptr) {
-  adr_status st = validate(scene, cam, p, out, ws);
-  if (st != ADR_OK) return st;
-  ws->last_vals = nullptr;  // no frame to differentiate until this one is enqueued whole
-  hipStream_t stream = (hipStream_t)stream_ptr;
-  const DeviceScene& s = scene->d;
-  const int W = cam->width, H = cam->height;
-
-  CamArgs ca = camera_args(cam, p);
-  const int64_t n_tiles = (int64_t)ca.tiles_x * ca.tiles_y;
-
-  CullArgs cu{};
-  cu.mode = p->cull;
-  cu.quad_cull = (p->flags & ADR_FLAG_NO_QUAD_CULL) ? 0 : 1;
-  cu.alpha_low = p->alpha_low;
-  cu.q_low = std::log2(p->alpha_low);
-  cu.lowpass = p->lowpass;
-
-  BlendArgs bl = blend_args(p);
-
-  if ((st = ensure_gauss(ws, s.n)) != ADR_OK) return st;
-  if ((st = grow(ws->ranges, ws->ranges_capacity, 2 * n_tiles, "ranges")) != ADR_OK) return st;
-  if ((st = grow(ws->tile_order, ws->tile_order_capacity, n_tiles, "tile order")) != ADR_OK) return st;
-  if ((st = grow(ws->order_counts, ws->order_counts_capacity, tile_order_scratch((int)n_tiles), "tile order counts")) !=
-      ADR_OK)
-    return st;
-  if ((st = grow(ws->wave_sums, ws->wave_sums_capacity, 16 * n_tiles, "load-sum partials")) != ADR_OK) return st;
-  const bool timing = (p->flags & ADR_FLAG_TIMING) != 0;
-  ws->timing_valid = false;
-  ws->last_stream = stream;
-  if (timing) ADR_HIP(hipEventRecord(ws->ev[0], stream));
-
-  // Clear the frame's counters, load sums and tile ranges: in the kernel that
-  // follows Preprocess when there is one and the ranges are small enough,
-  // else with a launch of their own.
-  const bool clear_in_notify = s.n > 0 && 2 * n_tiles <= kNotifyClearMax;
-  if (!clear_in_notify) ADR_HIP(launch_frame_init(ws, n_tiles, out->load_sums, stream));
-  // Stage 1: Preprocess (+ pair total and visible count)
-  ws->frame_seq += 1;
-  ADR_HIP(launch_preprocess(s, ca, cu, ws, clear_in_notify ? 2 * n_tiles : 0, out->load_sums, stream));
-  if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
-  // The pair count sizes everything after this point. The last Preprocess
-  // workgroup writes it to mapped host memory; wait for this frame's number.
-  unsigned long long n_pairs_u = 0, n_vis_u = 0, dmin = 0, dmax = 0;
-  if (s.n > 0) {
+// Waits for the pair count, visible count and depth-key range of frame
+// ws->frame_seq: spins on mapped host memory, or (fixed-memory workspace)
+// copies the device words back and waits for the stream.
+adr_status wait_notify(adr_workspace* ws, hipStream_t stream, unsigned long long v[kNotifySlots]) {
+  if (ws->notify_host) {
     volatile unsigned long long* nf = ws->notify_host;
     const auto t0 = std::chrono::steady_clock::now();
     while (nf[2] != ws->frame_seq) {
@@ -326,11 +456,60 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
       }
     }
     std::atomic_thread_fence(std::memory_order_acquire);
-    n_pairs_u = nf[0];
-    n_vis_u = nf[1];
-    dmin = nf[3];
-    dmax = nf[4];
+    for (int i = 0; i < kNotifySlots; ++i) v[i] = nf[i];
+    return ADR_OK;
   }
+  ADR_HIP(hipMemcpyAsync(v, ws->notify_slot, kNotifySlots * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         stream));
+  ADR_HIP(hipStreamSynchronize(stream));
+  if (v[2] != ws->frame_seq) {
+    set_error("adr_render: Preprocess did not report the pair count");
+    return ADR_E_HIP;
+  }
+  return ADR_OK;
+}
+
+}  // namespace
+
+namespace adr {
+
+adr_status render_prepare(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                          adr_frame* out, adr_workspace* ws, hipStream_t stream, FramePlan& plan) {
+  adr_status st;
+  ws->last_vals = nullptr;  // no frame to differentiate until this one is enqueued whole
+  const DeviceScene& s = scene->d;
+  plan.cam = camera_args(cam, p);
+  plan.n_tiles = (int64_t)plan.cam.tiles_x * plan.cam.tiles_y;
+  plan.cull = CullArgs{};
+  plan.cull.mode = p->cull;
+  plan.cull.quad_cull = (p->flags & ADR_FLAG_NO_QUAD_CULL) ? 0 : 1;
+  plan.cull.alpha_low = p->alpha_low;
+  plan.cull.q_low = std::log2(p->alpha_low);
+  plan.cull.lowpass = p->lowpass;
+  plan.blend = blend_args(p);
+  plan.want_load = out->load_sums != nullptr || out->load_stats != nullptr;
+  const CamArgs& ca = plan.cam;
+  const int64_t n_tiles = plan.n_tiles;
+
+  if ((st = ensure_capacity(ws, s.n, 0, n_tiles, stream)) != ADR_OK) return st;
+  const bool timing = (p->flags & ADR_FLAG_TIMING) != 0 && ws->ev[0] != nullptr;
+  ws->timing_valid = false;
+  ws->last_stream = stream;
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[0], stream));
+
+  // Clear the frame's counters, load accumulators and tile ranges: in the
+  // kernel that follows Preprocess when there is one and the ranges are small
+  // enough, else with a launch of their own.
+  const bool clear_in_notify = s.n > 0 && 2 * n_tiles <= kNotifyClearMax;
+  if (!clear_in_notify) ADR_HIP(launch_frame_init(ws, n_tiles, stream));
+  // Stage 1: Preprocess (+ pair total and visible count)
+  ws->frame_seq += 1;
+  ADR_HIP(launch_preprocess(s, ca, plan.cull, ws, clear_in_notify ? 2 * n_tiles : 0, stream));
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[1], stream));
+  // The pair count sizes everything after this point.
+  unsigned long long nv[kNotifySlots] = {};
+  if (s.n > 0 && (st = wait_notify(ws, stream, nv)) != ADR_OK) return st;
+  const unsigned long long n_pairs_u = nv[0], n_vis_u = nv[1], dmin = nv[3], dmax = nv[4];
   const int64_t n_vis = (int64_t)n_vis_u;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[2], stream));
   if (n_pairs_u >= (1ull << 32)) {
@@ -340,8 +519,9 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   }
   const int64_t n_pairs = (int64_t)n_pairs_u;
   out->n_pairs = n_pairs;
+  plan.n_pairs = n_pairs;
   ws->last_pairs = n_pairs;
-  if ((st = ensure_pairs(ws, n_pairs)) != ADR_OK) return st;
+  if ((st = ensure_capacity(ws, s.n, n_pairs, n_tiles, stream)) != ADR_OK) return st;
 
   // Stage 4a: every Gaussian by its 32-bit depth key (ties keep id order);
   // the visible ones come first. Only the bits that vary over the visible
@@ -350,8 +530,8 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   int dsorted = 0;  // which of the two buffers holds the result
   ws->last_depth_bits = 0;
   if (n_vis > 0) {
-    if (dmax < dmin || dmax > 0xffffffffull) {
-      set_error("adr_render: inconsistent depth-key range from Preprocess");
+    if (dmax < dmin || dmax > 0xffffffffull || n_vis > s.n) {
+      set_error("adr_render: inconsistent visible count or depth-key range from Preprocess");
       return ADR_E_HIP;
     }
     int dbits = bits_for((int64_t)(dmax - dmin) + 2);
@@ -359,7 +539,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     ws->last_depth_bits = dbits;
     const uint32_t lim = dbits >= 32 ? 0xffffffffu : (uint32_t)((1ull << dbits) - 1);
     // the last pass also lays tiles_touched out in depth order for the scan
-    ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, dbits, (uint32_t)dmin, lim, ws->sort_scratch,
+    ADR_HIP(launch_radix_sort(ws->depth.keys, ws->depth.vals, s.n, dbits, (uint32_t)dmin, lim, ws->depth_scratch,
                               ws->hists, &dsorted, stream, ws->dev_counters + kCntBadIndex, ws->touched,
                               ws->touched_sorted, s.n));
     if (s.n == 1)  // nothing to sort: the one Gaussian is its own order
@@ -377,26 +557,37 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   // Stage 4b: stable sort by tile id; equal tiles keep the depth order
   int psorted = 0;
   ADR_HIP(launch_radix_sort(ws->pairs.keys, ws->pairs.vals, n_pairs, bits_for(n_tiles), 0u, 0xffffffffu,
-                            ws->sort_scratch, ws->hists + kHistWords, &psorted, stream,
+                            ws->pair_scratch, ws->hists + kHistWords, &psorted, stream,
                             ws->dev_counters + kCntBadIndex));
-  const uint32_t* tiles = ws->pairs.keys[psorted];
-  const uint32_t* vals = ws->pairs.vals[psorted];
+  plan.tiles = ws->pairs.keys[psorted];
+  plan.vals = ws->pairs.vals[psorted];
   if (timing) ADR_HIP(hipEventRecord(ws->ev[6], stream));
   // Stage 5: IdentifyTileRanges
-  ADR_HIP(launch_tile_ranges(tiles, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
+  ADR_HIP(launch_tile_ranges(plan.tiles, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[7], stream));
-  // Stage 6: Render (tile order, blend, load sums)
+  // Stage 6, first part: the tiles' render order
   ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, ws->order_counts, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
-  ADR_HIP(launch_render(ws->rec, ws->exact, vals, ws->ranges, ws->tile_order, n_pairs, s.n, ca, bl, out, ws,
-                        stream));
+  return ADR_OK;
+}
+
+adr_status render_finish(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                         adr_frame* out, adr_workspace* ws, hipStream_t stream, const FramePlan& plan,
+                         bool blend_launched) {
+  const DeviceScene& s = scene->d;
+  const bool timing = (p->flags & ADR_FLAG_TIMING) != 0 && ws->ev[0] != nullptr;
+  if (!blend_launched)
+    ADR_HIP(launch_render(ws->rec, ws->exact, plan.vals, ws->ranges, ws->tile_order, plan.n_pairs, s.n, plan.cam,
+                          plan.blend, out, plan.want_load, ws, stream));
   ws->last_scene = scene;
   ws->last_scene_uid = scene->uid;
   ws->last_cam = *cam;
   ws->last_params = *p;
-  ws->last_vals = vals;
+  ws->last_vals = plan.vals;
   if (timing) ADR_HIP(hipEventRecord(ws->ev[9], stream));
-  ADR_HIP(launch_load_sums(ws, (int)n_tiles, out->load_sums, stream));
+  if (plan.want_load)
+    ADR_HIP(launch_load_sums(ws, (int)plan.n_tiles, (int64_t)cam->width * cam->height, out->load_sums,
+                             out->load_stats, stream));
   if (timing) {
     ADR_HIP(hipEventRecord(ws->ev[10], stream));
     ws->timing_valid = true;
@@ -407,19 +598,31 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     ADR_HIP(hipMemcpyAsync(out->tiles_touched, ws->touched, (size_t)s.n * sizeof(uint32_t),
                            hipMemcpyDeviceToDevice, stream));
   if (out->ranges)
-    ADR_HIP(hipMemcpyAsync(out->ranges, ws->ranges, (size_t)n_tiles * 2 * sizeof(uint32_t),
+    ADR_HIP(hipMemcpyAsync(out->ranges, ws->ranges, (size_t)plan.n_tiles * 2 * sizeof(uint32_t),
                            hipMemcpyDeviceToDevice, stream));
   if (out->keys || out->values) {
-    if (n_pairs > out->pair_capacity) {
+    if (plan.n_pairs > out->pair_capacity) {
       set_error("adr_render: pair_capacity smaller than the frame's pair count (see n_pairs)");
       return ADR_E_WORKSPACE;
     }
-    if (out->keys) ADR_HIP(launch_compose_keys(tiles, vals, ws->rec, n_pairs, s.n, out->keys, stream));
-    if (out->values && n_pairs > 0)
-      ADR_HIP(hipMemcpyAsync(out->values, vals, (size_t)n_pairs * sizeof(uint32_t), hipMemcpyDeviceToDevice,
-                             stream));
+    if (out->keys) ADR_HIP(launch_compose_keys(plan.tiles, plan.vals, ws->rec, plan.n_pairs, s.n, out->keys, stream));
+    if (out->values && plan.n_pairs > 0)
+      ADR_HIP(hipMemcpyAsync(out->values, plan.vals, (size_t)plan.n_pairs * sizeof(uint32_t),
+                             hipMemcpyDeviceToDevice, stream));
   }
   return ADR_OK;
+}
+
+}  // namespace adr
+
+extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* p,
+                                 adr_frame* out, adr_workspace* ws, void* stream_ptr) {
+  adr_status st = validate(scene, cam, p, out, ws);
+  if (st != ADR_OK) return st;
+  hipStream_t stream = (hipStream_t)stream_ptr;
+  FramePlan plan;
+  if ((st = render_prepare(scene, cam, p, out, ws, stream, plan)) != ADR_OK) return st;
+  return render_finish(scene, cam, p, out, ws, stream, plan, false);
 }
 
 namespace {
@@ -452,15 +655,15 @@ extern "C" adr_status adr_render_backward_load(const adr_scene* scene, const adr
     return ADR_E_INVALID;
   }
   if (ws->last_scene != scene || ws->last_scene_uid != scene->uid || !same_camera(ws->last_cam, *cam) ||
-      !same_params(ws->last_params, *p) ||
-      !ws->last_vals) {
+      !same_params(ws->last_params, *p) || !ws->last_vals) {
     set_error("adr_render_backward: the last adr_render on this workspace was not this scene, camera and params");
     return ADR_E_INVALID;
   }
   hipStream_t stream = (hipStream_t)stream_ptr;
   const DeviceScene& s = scene->d;
   if (s.n == 0) return ADR_OK;
-  if ((st = grow(ws->grad2d, ws->grad2d_capacity, (int64_t)kGrad2d * s.n, "screen-space gradients")) != ADR_OK)
+  if ((st = grow_arena(ws, ws->grad_arena, ws->grad_capacity, s.n, carve_grad_arena, true, true, stream,
+                       "screen-space gradients")) != ADR_OK)
     return st;
   ADR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(ws->grad2d), 0u, (int64_t)kGrad2d * s.n, stream));
   CamArgs ca = camera_args(cam, p);
@@ -496,7 +699,7 @@ extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32
 }
 
 extern "C" int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n) {
-  if (!ws || !out || n <= 0) return 0;
+  if (!ws || !out || n <= 0 || !ws->dev_counters) return 0;
   if (hipStreamSynchronize(ws->last_stream) != hipSuccess ||
       hipMemcpy(ws->host_counters, ws->dev_counters, kCounterSlots * sizeof(unsigned long long),
                 hipMemcpyDeviceToHost) != hipSuccess) {

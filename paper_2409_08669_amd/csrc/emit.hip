@@ -80,17 +80,17 @@ __global__ void __launch_bounds__(256) compose_keys_kernel(const uint32_t* __res
 }
 
 // Clears everything a frame accumulates into: counters, sort histograms,
-// the caller's load sums and the tile ranges (empty tiles keep (0, 0)).
+// the load accumulators and the tile ranges (empty tiles keep (0, 0)).
 // Used when the kernel after Preprocess cannot do it: an empty scene (no
 // Preprocess) or more tile-range words than that one workgroup clears.
 __global__ void __launch_bounds__(256) frame_init_kernel(unsigned long long* __restrict__ counters,
                                                          uint32_t* __restrict__ hists,
-                                                         unsigned long long* __restrict__ load_sums,
+                                                         unsigned long long* __restrict__ load_acc,
                                                          uint32_t* __restrict__ ranges, int64_t n_ranges) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < kCounterSlots) counters[i] = 0ull;
   if (i < 2 * kHistWords) hists[i] = 0u;
-  if (load_sums && i < 4) load_sums[i] = 0ull;
+  if (i < kLoadAccWords) load_acc[i] = 0ull;
   if (i < n_ranges) ranges[i] = 0u;
 }
 
@@ -138,11 +138,12 @@ hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, cons
   return hipGetLastError();
 }
 
-hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, uint64_t* load_sums, hipStream_t stream) {
+hipError_t launch_frame_init(adr_workspace* ws, int64_t n_tiles, hipStream_t stream) {
+  if (n_tiles > ws->tile_capacity) return hipErrorInvalidValue;
   int64_t n = 2 * n_tiles;
   if (n < 2 * kHistWords) n = 2 * kHistWords;
-  frame_init_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, stream>>>(
-      ws->dev_counters, ws->hists, (unsigned long long*)load_sums, ws->ranges, 2 * n_tiles);
+  frame_init_kernel<<<dim3((unsigned)((n + 255) / 256)), 256, 0, stream>>>(ws->dev_counters, ws->hists, ws->load_acc,
+                                                                           ws->ranges, 2 * n_tiles);
   return hipGetLastError();
 }
 

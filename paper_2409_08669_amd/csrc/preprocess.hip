@@ -19,13 +19,12 @@ struct ShConsts {
 
 // Colour from K = (d+1)^2 SH coefficients. All 3K loads are issued before
 // any arithmetic (one memory round trip per Gaussian).
-template <int K>
-__device__ __forceinline__ void sh_colour_k(const float* __restrict__ planes, int64_t n, int64_t g,
-                                            const ShConsts& kc, float x, float y, float z, float& r, float& gr,
-                                            float& b) {
+template <int K, class Src>
+__device__ __forceinline__ void sh_colour_k(const Src& src, int64_t g, const ShConsts& kc, float x, float y,
+                                            float z, float& r, float& gr, float& b) {
   float coef[3 * K];
 #pragma unroll
-  for (int i = 0; i < 3 * K; ++i) coef[i] = planes[(int64_t)i * n + g];
+  for (int i = 0; i < 3 * K; ++i) coef[i] = src.coef(i, g);
   // Polynomial parts P_l^|m|(cos th) cos(m ph) / sin(|m| ph) on the unit
   // sphere, Condon-Shortley phase included; index l*l + l + m.
   float basis[16];
@@ -65,14 +64,14 @@ __device__ __forceinline__ void sh_colour_k(const float* __restrict__ planes, in
   b = fmaxf(acc[2] + 0.5f, 0.f);
 }
 
-__device__ __forceinline__ void sh_colour(const float* __restrict__ planes, int64_t n, int64_t g, int n_coeff,
-                                          const ShConsts& kc, float x, float y, float z, float& r, float& gr,
-                                          float& b) {
+template <class Src>
+__device__ __forceinline__ void sh_colour(const Src& src, int64_t g, int n_coeff, const ShConsts& kc, float x,
+                                          float y, float z, float& r, float& gr, float& b) {
   switch (n_coeff) {
-    case 1: sh_colour_k<1>(planes, n, g, kc, x, y, z, r, gr, b); break;
-    case 4: sh_colour_k<4>(planes, n, g, kc, x, y, z, r, gr, b); break;
-    case 9: sh_colour_k<9>(planes, n, g, kc, x, y, z, r, gr, b); break;
-    default: sh_colour_k<16>(planes, n, g, kc, x, y, z, r, gr, b); break;
+    case 1: sh_colour_k<1>(src, g, kc, x, y, z, r, gr, b); break;
+    case 4: sh_colour_k<4>(src, g, kc, x, y, z, r, gr, b); break;
+    case 9: sh_colour_k<9>(src, g, kc, x, y, z, r, gr, b); break;
+    default: sh_colour_k<16>(src, g, kc, x, y, z, r, gr, b); break;
   }
 }
 
@@ -188,9 +187,9 @@ __device__ __forceinline__ void principal_axes(double ca, double cb, double cc, 
   a2 = pg + t * pb;
 }
 
+template <class Src>
 __global__ void __launch_bounds__(256) preprocess_kernel(
-    const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
-    const float* __restrict__ planes, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, CullArgs cull,
+    Src src, int64_t n, int n_coeff, ShConsts shc, CamArgs cam, CullArgs cull,
     RenderRecord* __restrict__ rec, ExactRecord* __restrict__ exact, uint2* __restrict__ tile_rect,
     uint32_t* __restrict__ depth_key, uint32_t* __restrict__ depth_id, uint32_t* __restrict__ touched_out,
     ulonglong4* __restrict__ block_parts) {
@@ -199,9 +198,9 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
   uint32_t dkey = 0xffffffffu;  // Gaussians without pairs sort after every visible one
   if (g < n) {
     // all three geometry loads up front: one round trip
-    const float4 ga = geo_a[g];
-    const float4 gb = geo_b[g];
-    const float4 gq = geo_q[g];
+    const float4 ga = src.a(g);
+    const float4 gb = src.b(g);
+    const float4 gq = src.q(g);
     const double mx = ga.x, my = ga.y, mz = ga.z;
     const double px = cam.r[0] * mx + cam.r[1] * my + cam.r[2] * mz + cam.t[0];
     const double py = cam.r[3] * mx + cam.r[4] * my + cam.r[5] * mz + cam.t[1];
@@ -300,7 +299,7 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
           double vx = mx - cam.cam_pos[0], vy = my - cam.cam_pos[1], vz = mz - cam.cam_pos[2];
           const double vn = 1.0 / sqrt(vx * vx + vy * vy + vz * vz);
           float cr, cg, cbl;
-          sh_colour(planes, n, g, n_coeff, shc, (float)(vx * vn), (float)(vy * vn), (float)(vz * vn), cr, cg, cbl);
+          sh_colour(src, g, n_coeff, shc, (float)(vx * vn), (float)(vy * vn), (float)(vz * vn), cr, cg, cbl);
           double rc, rs, a1, a2;
           principal_axes(ca, cb, cc, rc, rs, a1, a2);
           const double ql = log2(op);
@@ -367,13 +366,13 @@ __global__ void __launch_bounds__(256) preprocess_kernel(
 // hands the pair count, the visible count and the visible depth-key range to
 // the host through mapped pinned memory, then publishes the frame's number.
 // It also clears what the rest of the frame accumulates into (the tile
-// ranges, the blend's FP64 counters, the caller's load sums) when n_ranges > 0.
+// ranges, the blend's FP64 counters, the load accumulators) when n_ranges > 0.
 __global__ void __launch_bounds__(1024) notify_host_kernel(const ulonglong4* __restrict__ block_parts, int nb,
                                                            unsigned long long* __restrict__ counters,
                                                            unsigned long long* __restrict__ notify,
                                                            unsigned long long seq, uint32_t* __restrict__ ranges,
                                                            int64_t n_ranges,
-                                                           unsigned long long* __restrict__ load_sums) {
+                                                           unsigned long long* __restrict__ load_acc) {
   __shared__ unsigned long long red[4][16];
   for (int64_t i = threadIdx.x; i < n_ranges; i += blockDim.x) ranges[i] = 0u;
   if (n_ranges > 0) {
@@ -382,7 +381,7 @@ __global__ void __launch_bounds__(1024) notify_host_kernel(const ulonglong4* __r
       counters[kCntReplay] = 0ull;
       counters[kCntBadIndex] = 0ull;
     }
-    if (load_sums && threadIdx.x < 4) load_sums[threadIdx.x] = 0ull;
+    if (threadIdx.x < kLoadAccWords) load_acc[threadIdx.x] = 0ull;
   }
   unsigned long long t = 0, v = 0, mn = ~0ull, mx = 0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -460,10 +459,9 @@ static ShConsts make_sh_consts() {
 //   x, y    = f p_{x,y}/p_z + c - 1/2;  p = W mean + t;
 //   Sigma   = M M^T, M = R(q / |q|) diag(exp(log_scale)).
 // Gaussians behind the near plane or with a degenerate Sigma' get zeros.
-template <int K>
+template <int K, class Src>
 __global__ void __launch_bounds__(256) preprocess_backward_kernel(
-    const float4* __restrict__ geo_a, const float4* __restrict__ geo_b, const float4* __restrict__ geo_q,
-    const float* __restrict__ planes, int64_t n, ShConsts shc, CamArgs cam, double lowpass,
+    Src src, int64_t n, ShConsts shc, CamArgs cam, double lowpass,
     const float* __restrict__ grad2d, float* __restrict__ d_means, float* __restrict__ d_log_scales,
     float* __restrict__ d_quats, float* __restrict__ d_logits, float* __restrict__ d_sh) {
   using real = float;  // gradients need ~1e-4 relative accuracy: FP32 throughout
@@ -481,7 +479,7 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
 #pragma unroll
   for (int i = 0; i < 3 * K; ++i) my_sh[i] = 0.f;
   if (g < n) {
-  const float4 ga = geo_a[g], gb = geo_b[g], gq = geo_q[g];
+  const float4 ga = src.a(g), gb = src.b(g), gq = src.q(g);
   const real mx = ga.x, my = ga.y, mz = ga.z;
   real W[9];
 #pragma unroll
@@ -567,7 +565,7 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     }
     float coef[3 * K];  // all SH loads issued together
 #pragma unroll
-    for (int i = 0; i < 3 * K; ++i) coef[i] = planes[(int64_t)i * n + g];
+    for (int i = 0; i < 3 * K; ++i) coef[i] = src.coef(i, g);
     real raw[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -712,35 +710,51 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
 
 int64_t preprocess_blocks(int64_t n) { return (n + 255) / 256; }
 
+PlanarScene planar(const DeviceScene& s) { return PlanarScene{s.geo_a, s.geo_b, s.geo_q, s.sh, s.n}; }
+RowMajorScene row_major(const DeviceScene& s) {
+  return RowMajorScene{s.means, s.log_scales, s.quats, s.logits, s.sh_rows, 3 * s.n_coeff};
+}
+
 hipError_t launch_preprocess(const DeviceScene& s, const CamArgs& cam, const CullArgs& cull, adr_workspace* ws,
-                             int64_t n_ranges, uint64_t* load_sums, hipStream_t stream) {
+                             int64_t n_ranges, hipStream_t stream) {
   if (s.n == 0) return hipSuccess;
   static const ShConsts shc = make_sh_consts();
   const int64_t nb = preprocess_blocks(s.n);
-  if (nb > ws->block_parts_capacity) return hipErrorInvalidValue;
-  preprocess_kernel<<<dim3((unsigned)nb), 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, s.n_coeff, shc,
-                                                            cam, cull, ws->rec, ws->exact, ws->tile_rect,
-                                                            ws->depth.keys[0], ws->depth.vals[0], ws->touched,
-                                                            ws->block_parts);
-  if (n_ranges > kNotifyClearMax) return hipErrorInvalidValue;
+  if (s.n > ws->gauss_capacity || 2 * (int64_t)cam.tiles_x * cam.tiles_y > 2 * ws->tile_capacity ||
+      n_ranges > kNotifyClearMax)
+    return hipErrorInvalidValue;
+  if (s.borrowed)
+    preprocess_kernel<<<dim3((unsigned)nb), 256, 0, stream>>>(row_major(s), s.n, s.n_coeff, shc, cam, cull, ws->rec,
+                                                              ws->exact, ws->tile_rect, ws->depth.keys[0],
+                                                              ws->depth.vals[0], ws->touched, ws->block_parts);
+  else
+    preprocess_kernel<<<dim3((unsigned)nb), 256, 0, stream>>>(planar(s), s.n, s.n_coeff, shc, cam, cull, ws->rec,
+                                                              ws->exact, ws->tile_rect, ws->depth.keys[0],
+                                                              ws->depth.vals[0], ws->touched, ws->block_parts);
   notify_host_kernel<<<1, 1024, 0, stream>>>(ws->block_parts, (int)nb, ws->dev_counters, ws->notify_dev,
-                                             ws->frame_seq, ws->ranges, n_ranges,
-                                             (unsigned long long*)load_sums);
+                                             ws->frame_seq, ws->ranges, n_ranges, ws->load_acc);
+  return hipGetLastError();
+}
+
+template <class Src>
+hipError_t launch_preprocess_backward_src(const Src& src, int64_t n, int n_coeff, const CamArgs& cam, double lowpass,
+                                          const float* grad2d, const adr_scene_grads& out, hipStream_t stream) {
+  static const ShConsts shc = make_sh_consts();
+  auto* kernel = n_coeff == 1   ? preprocess_backward_kernel<1, Src>
+                 : n_coeff == 4 ? preprocess_backward_kernel<4, Src>
+                 : n_coeff == 9 ? preprocess_backward_kernel<9, Src>
+                                : preprocess_backward_kernel<16, Src>;
+  kernel<<<dim3((unsigned)preprocess_blocks(n)), 256, 0, stream>>>(src, n, shc, cam, lowpass, grad2d, out.d_means,
+                                                                    out.d_log_scales, out.d_quats,
+                                                                    out.d_opacity_logits, out.d_sh);
   return hipGetLastError();
 }
 
 hipError_t launch_preprocess_backward(const DeviceScene& s, const CamArgs& cam, double lowpass, const float* grad2d,
                                       const adr_scene_grads& out, hipStream_t stream) {
   if (s.n == 0) return hipSuccess;
-  static const ShConsts shc = make_sh_consts();
-  auto* kernel = s.n_coeff == 1   ? preprocess_backward_kernel<1>
-                 : s.n_coeff == 4 ? preprocess_backward_kernel<4>
-                 : s.n_coeff == 9 ? preprocess_backward_kernel<9>
-                                  : preprocess_backward_kernel<16>;
-  kernel<<<dim3((unsigned)preprocess_blocks(s.n)), 256, 0, stream>>>(s.geo_a, s.geo_b, s.geo_q, s.sh, s.n, shc, cam,
-                                                                      lowpass, grad2d, out.d_means, out.d_log_scales,
-                                                                      out.d_quats, out.d_opacity_logits, out.d_sh);
-  return hipGetLastError();
+  if (s.borrowed) return launch_preprocess_backward_src(row_major(s), s.n, s.n_coeff, cam, lowpass, grad2d, out, stream);
+  return launch_preprocess_backward_src(planar(s), s.n, s.n_coeff, cam, lowpass, grad2d, out, stream);
 }
 
 }  // namespace adr

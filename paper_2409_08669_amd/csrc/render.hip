@@ -395,29 +395,39 @@ __device__ __forceinline__ uint64_t blend_step(Pixel& px, const float4& A, const
   return blend_m & ((__ballot(Tn < bl.t_min) ^ stop_fix) | (kCap ? __ballot(px.nb == cap) : 0ull));
 }
 
+// LDS of one tile's workgroup: per wave, per batch slot (= list position -
+// batch start), the staged record, its colour and its Gaussian id (slot 64 is
+// a null record), and per step i of the candidate pass a word whose byte t is
+// the slot of sub-block t's i-th entry (64 past the end of its list; word 64
+// is all 64).
+struct TileLds {
+  Staged stage[4][65];
+  float4 stage_col[4][65];
+  uint32_t stage_gid[4][65];
+  uint32_t step_table[4][65];
+};
+
+// The blend of the tile at position blk of the frame's tile order, by the
+// 256 lanes of the calling workgroup.
 template <bool kCap>
-__global__ void __launch_bounds__(256, 4) render_kernel(
-    const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, uint32_t n_pairs, uint32_t n_gauss,
-    CamArgs cam, BlendArgs bl, int n_tiles, float* __restrict__ image, float* __restrict__ final_t,
-    uint32_t* __restrict__ l_iter, uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums,
-    unsigned long long* __restrict__ counters) {
-  // per wave, per batch slot (= list position - batch start): the staged
-  // record, its colour and its Gaussian id; slot 64 is a null record
-  __shared__ Staged stage[4][65];
-  __shared__ float4 stage_col[4][65];
-  __shared__ uint32_t stage_gid[4][65];
-  // per wave, per step i of the candidate pass: byte t = the slot of sub-block
-  // t's i-th entry (64 past the end of its list); word 64 is all 64
-  __shared__ uint32_t step_table[4][65];
-  const int tile = (int)min(order[blockIdx.x], (uint32_t)(n_tiles - 1));
+__device__ __forceinline__ void render_tile(
+    TileLds& lds, const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact,
+    const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order,
+    uint32_t n_pairs, uint32_t n_gauss, const CamArgs& cam, const BlendArgs& bl, int n_tiles, int blk,
+    float* __restrict__ image, float* __restrict__ final_t, uint32_t* __restrict__ l_iter,
+    uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums, unsigned long long* __restrict__ counters) {
+  auto& stage = lds.stage;
+  auto& stage_col = lds.stage_col;
+  auto& stage_gid = lds.stage_gid;
+  auto& step_table = lds.step_table;
+  const int tile = (int)min(order[blk], (uint32_t)(n_tiles - 1));
   const int W = cam.width, H = cam.height;
   const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int qx0 = tx * kTile + (wid & 1) * kQuad;
   const int qy0 = ty * kTile + (wid >> 1) * kQuad;
   if (qx0 >= W || qy0 >= H) {  // quadrant entirely outside the image (wave-uniform)
-    if (wave_sums && lane == 0) wave_sums[4 * blockIdx.x + wid] = make_ulonglong4(0ull, 0ull, 0ull, 0ull);
+    if (wave_sums && lane == 0) wave_sums[4 * blk + wid] = make_ulonglong4(0ull, 0ull, 0ull, 0ull);
     return;
   }
   // lane -> pixel: sub-block sb = lane / 16 at (4 (sb & 1), 4 (sb >> 1)) in the quadrant
@@ -657,7 +667,7 @@ finished:
     // per-wave partial sums for Eq. 13, reduced by load_sums_kernel
     const unsigned long long b1 = wave_sum_u64(px.nb), b2 = wave_sum_u64((unsigned long long)px.nb * px.nb);
     const unsigned long long i1 = wave_sum_u64(ni), i2 = wave_sum_u64((unsigned long long)ni * ni);
-    if (lane == 0) wave_sums[4 * blockIdx.x + wid] = make_ulonglong4(b1, b2, i1, i2);
+    if (lane == 0) wave_sums[4 * blk + wid] = make_ulonglong4(b1, b2, i1, i2);
   }
   if (counters) {
     const unsigned long long nbd = wave_sum_u64(px.n_rare & 0xffffu), nrp = wave_sum_u64(px.n_rare >> 16);
@@ -668,11 +678,63 @@ finished:
   }
 }
 
-// Adds the per-wave partials into the four load sums (zeroed at the start of
-// the frame). Integer sums: the result does not depend on the order.
+template <bool kCap>
+__global__ void __launch_bounds__(256, 4) render_kernel(
+    const RenderRecord* __restrict__ rec, const ExactRecord* __restrict__ exact, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ order, uint32_t n_pairs, uint32_t n_gauss,
+    CamArgs cam, BlendArgs bl, int n_tiles, float* __restrict__ image, float* __restrict__ final_t,
+    uint32_t* __restrict__ l_iter, uint32_t* __restrict__ l_blend, ulonglong4* __restrict__ wave_sums,
+    unsigned long long* __restrict__ counters) {
+  __shared__ TileLds lds;
+  render_tile<kCap>(lds, rec, exact, vals, ranges, order, n_pairs, n_gauss, cam, bl, n_tiles, (int)blockIdx.x, image,
+                    final_t, l_iter, l_blend, wave_sums, counters);
+}
+
+// The blends of several frames in one launch: workgroup b renders item
+// b - block_base of the job whose [block_base, block_base + n_tiles) holds b
+// (jobs in ascending block_base). Every frame's tiles are computed exactly as
+// render_kernel computes them alone.
+template <bool kCap>
+__global__ void __launch_bounds__(256, 4) render_batch_kernel(const BlendJob* __restrict__ jobs, int n_jobs) {
+  __shared__ TileLds lds;
+  const int b = (int)blockIdx.x;
+  int j = 0;
+  for (int k = 1; k < n_jobs; ++k)
+    if (b >= jobs[k].block_base) j = k;
+  const BlendJob& job = jobs[j];
+  const int blk = b - job.block_base;
+  if (blk < 0 || blk >= job.n_tiles) return;  // (cannot happen for a consistent table)
+  render_tile<kCap>(lds, job.rec, job.exact, job.vals, job.ranges, job.order, job.n_pairs, job.n_gauss, job.cam,
+                    job.blend, job.n_tiles, blk, job.image, job.final_t, job.l_iter, job.l_blend, job.wave_sums,
+                    job.counters);
+}
+
+// Mean and population standard deviation of a per-pixel load over n pixels
+// (Eq. 13) from its exact integer sums s1 = sum l, s2 = sum l^2: the variance
+// numerator n s2 - s1^2 is formed exactly in 128-bit integers (it is >= 0),
+// then divided by n^2 in FP64.
+__device__ void load_moments(unsigned long long s1, unsigned long long s2, unsigned long long n, double* out) {
+  const unsigned long long a_lo = n * s2, a_hi = __umul64hi(n, s2);
+  const unsigned long long b_lo = s1 * s1, b_hi = __umul64hi(s1, s1);
+  const unsigned long long d_lo = a_lo - b_lo;
+  const unsigned long long d_hi = a_hi - b_hi - (a_lo < b_lo ? 1ull : 0ull);
+  const double num = (double)d_hi * 18446744073709551616.0 + (double)d_lo;
+  const double nn = (double)n;
+  out[0] = (double)s1 / nn;
+  out[1] = sqrt(num / (nn * nn));
+}
+
+// Adds the per-wave partials into the four load accumulators (zeroed at the
+// start of the frame; integer sums, so the result does not depend on the
+// order). The last workgroup to finish copies the sums to the caller and
+// turns them into the load statistics of Eq. 13.
 __global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __restrict__ wave_sums, int n,
-                                                        unsigned long long* __restrict__ out) {
+                                                        unsigned long long* __restrict__ acc,
+                                                        unsigned long long n_pixels,
+                                                        unsigned long long* __restrict__ sums_out,
+                                                        double* __restrict__ stats_out) {
   __shared__ unsigned long long part[4][4];
+  __shared__ bool last;
   unsigned long long a = 0, b = 0, c = 0, d = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const ulonglong4 v = wave_sums[i];
@@ -696,7 +758,23 @@ __global__ void __launch_bounds__(256) load_sums_kernel(const ulonglong4* __rest
   if (threadIdx.x < 4) {
     const unsigned long long t = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
                                  part[3][threadIdx.x];
-    if (t) atomicAdd(&out[threadIdx.x], t);
+    if (t) atomicAdd(&acc[threadIdx.x], t);
+  }
+  // every sum of this workgroup is in acc before its ticket is taken
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&acc[4], 1ull) == (unsigned long long)gridDim.x - 1;
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    unsigned long long v[4];
+    for (int k = 0; k < 4; ++k) v[k] = __hip_atomic_load(&acc[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (sums_out)
+      for (int k = 0; k < 4; ++k) sums_out[k] = v[k];
+    if (stats_out) {
+      load_moments(v[0], v[1], n_pixels, stats_out);
+      load_moments(v[2], v[3], n_pixels, stats_out + 2);
+    }
   }
 }
 
@@ -889,10 +967,11 @@ hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tile
 
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
                          const uint32_t* ranges, const uint32_t* order, int64_t n_pairs, int64_t n_gauss,
-                         const CamArgs& cam, const BlendArgs& blend, adr_frame* out, adr_workspace* ws,
-                         hipStream_t stream) {
+                         const CamArgs& cam, const BlendArgs& blend, const adr_frame* out, bool want_load,
+                         adr_workspace* ws, hipStream_t stream) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  ulonglong4* ws4 = out->load_sums ? (ulonglong4*)ws->wave_sums : nullptr;
+  if (n_tiles > ws->tile_capacity) return hipErrorInvalidValue;
+  ulonglong4* ws4 = want_load ? (ulonglong4*)ws->wave_sums : nullptr;
   auto* kernel = blend.lb_cap > 0 ? render_kernel<true> : render_kernel<false>;
   kernel<<<dim3((unsigned)n_tiles), 256, 0, stream>>>(
       rec, exact, vals, ranges, order, (uint32_t)n_pairs, (uint32_t)(n_gauss > 0 ? n_gauss : 1), cam, blend,
@@ -900,13 +979,52 @@ hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, cons
   return hipGetLastError();
 }
 
-hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, uint64_t* load_sums, hipStream_t stream) {
-  if (!load_sums) return hipSuccess;
+hipError_t launch_render_batch(const BlendJob* jobs_dev, int n_jobs, int64_t total_blocks, bool any_cap,
+                               hipStream_t stream) {
+  if (n_jobs <= 0 || total_blocks <= 0) return hipSuccess;
+  if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
+  auto* kernel = any_cap ? render_batch_kernel<true> : render_batch_kernel<false>;
+  kernel<<<dim3((unsigned)total_blocks), 256, 0, stream>>>(jobs_dev, n_jobs);
+  return hipGetLastError();
+}
+
+BlendJob make_blend_job(const adr_workspace* ws, const RenderRecord* rec, const ExactRecord* exact,
+                        const uint32_t* vals, const CamArgs& cam, const BlendArgs& blend, int64_t n_pairs,
+                        int64_t n_gauss, const adr_frame* out, bool want_load) {
+  BlendJob j{};
+  j.rec = rec;
+  j.exact = exact;
+  j.vals = vals;
+  j.ranges = ws->ranges;
+  j.order = ws->tile_order;
+  j.image = out->image;
+  j.final_t = out->final_t;
+  j.l_iter = out->l_iter;
+  j.l_blend = out->l_blend;
+  j.wave_sums = want_load ? (ulonglong4*)ws->wave_sums : nullptr;
+  j.counters = ws->dev_counters;
+  j.n_pairs = (uint32_t)n_pairs;
+  j.n_gauss = (uint32_t)(n_gauss > 0 ? n_gauss : 1);
+  j.n_tiles = cam.tiles_x * cam.tiles_y;
+  j.block_base = 0;
+  j.cam = cam;
+  j.blend = blend;
+  // a cap of 0 is "off": the capped kernel then compares against a count no pixel reaches
+  if (j.blend.lb_cap <= 0) j.blend.lb_cap = 0;
+  return j;
+}
+
+hipError_t launch_load_sums(adr_workspace* ws, int n_tiles, int64_t n_pixels, uint64_t* load_sums,
+                            double* load_stats, hipStream_t stream) {
+  if (!load_sums && !load_stats) return hipSuccess;
+  if (n_tiles > ws->tile_capacity || n_pixels <= 0) return hipErrorInvalidValue;
   const int n = 4 * n_tiles;
   int blocks = (n + 1023) / 1024;
   if (blocks > 64) blocks = 64;
-  load_sums_kernel<<<dim3((unsigned)blocks), 256, 0, stream>>>((const ulonglong4*)ws->wave_sums, n,
-                                                               (unsigned long long*)load_sums);
+  if (blocks < 1) blocks = 1;
+  load_sums_kernel<<<dim3((unsigned)blocks), 256, 0, stream>>>((const ulonglong4*)ws->wave_sums, n, ws->load_acc,
+                                                               (unsigned long long)n_pixels,
+                                                               (unsigned long long*)load_sums, load_stats);
   return hipGetLastError();
 }
 

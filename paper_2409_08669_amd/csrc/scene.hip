@@ -41,17 +41,42 @@ using namespace adr;
 
 namespace {
 
-void free_scene(DeviceScene& d) {
-  if (d.geo_a) (void)hipFree(d.geo_a);
-  if (d.geo_b) (void)hipFree(d.geo_b);
-  if (d.geo_q) (void)hipFree(d.geo_q);
-  if (d.sh) (void)hipFree(d.sh);
+void* scene_alloc(const adr_allocator& a, size_t bytes) {
+  if (a.alloc) return a.alloc(bytes, nullptr, a.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void scene_free(const adr_allocator& a, void* p, size_t bytes) {
+  if (!p) return;
+  if (a.alloc)
+    a.free(p, bytes, nullptr, a.ctx);
+  else
+    (void)hipFree(p);
+}
+
+void free_scene(adr_scene* s) {
+  DeviceScene& d = s->d;
+  if (!d.borrowed) {
+    const size_t n_alloc = (size_t)(d.n > 0 ? d.n : 1);
+    scene_free(s->alloc, d.geo_a, n_alloc * sizeof(float4));
+    scene_free(s->alloc, d.geo_b, n_alloc * sizeof(float4));
+    scene_free(s->alloc, d.geo_q, n_alloc * sizeof(float4));
+    scene_free(s->alloc, d.sh, n_alloc * 3 * d.n_coeff * sizeof(float));
+  }
   d = DeviceScene{};
 }
 
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
 }  // namespace
 
-extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** out) {
+extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, const adr_allocator* allocator,
+                                       adr_scene** out) {
   if (!desc || !out) {
     set_error("adr_create_scene: NULL argument");
     return ADR_E_INVALID;
@@ -69,6 +94,20 @@ extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** o
     set_error("adr_create_scene: NULL array with n > 0");
     return ADR_E_INVALID;
   }
+  if (allocator && (!allocator->alloc || !allocator->free)) {
+    set_error("adr_create_scene: an allocator needs both alloc and free");
+    return ADR_E_INVALID;
+  }
+  if (desc->borrow && !desc->pointers_on_device) {
+    set_error("adr_create_scene: borrow = 1 needs device pointers");
+    return ADR_E_INVALID;
+  }
+  if (desc->borrow && desc->n > 0 &&
+      (!aligned(desc->quats, 16) || !aligned(desc->means, 4) || !aligned(desc->log_scales, 4) ||
+       !aligned(desc->opacity_logits, 4) || !aligned(desc->sh, 4))) {
+    set_error("adr_create_scene: a borrowed scene needs 16-byte aligned quats and 4-byte aligned arrays");
+    return ADR_E_INVALID;
+  }
   static std::atomic<uint64_t> next_uid{1};
   adr_scene* s = new (std::nothrow) adr_scene();
   if (!s) {
@@ -76,19 +115,32 @@ extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** o
     return ADR_E_OOM;
   }
   s->uid = next_uid.fetch_add(1);
+  if (allocator) s->alloc = *allocator;
   DeviceScene& d = s->d;
   d.n = desc->n;
   d.sh_degree = desc->sh_degree;
   d.n_coeff = (desc->sh_degree + 1) * (desc->sh_degree + 1);
   const int64_t n = desc->n;
+  if (desc->borrow) {
+    // zero-copy: every render reads the caller's row-major arrays
+    d.borrowed = true;
+    d.means = desc->means;
+    d.log_scales = desc->log_scales;
+    d.quats = desc->quats;
+    d.logits = desc->opacity_logits;
+    d.sh_rows = desc->sh;
+    d.bytes = 0;
+    *out = s;
+    return ADR_OK;
+  }
   const size_t n_alloc = (size_t)(n > 0 ? n : 1);
   const size_t sh_floats = n_alloc * 3 * d.n_coeff;
-  if (hipMalloc(&d.geo_a, n_alloc * sizeof(float4)) != hipSuccess ||
-      hipMalloc(&d.geo_b, n_alloc * sizeof(float4)) != hipSuccess ||
-      hipMalloc(&d.geo_q, n_alloc * sizeof(float4)) != hipSuccess ||
-      hipMalloc(&d.sh, sh_floats * sizeof(float)) != hipSuccess) {
-    (void)hipGetLastError();
-    free_scene(d);
+  d.geo_a = static_cast<float4*>(scene_alloc(s->alloc, n_alloc * sizeof(float4)));
+  d.geo_b = static_cast<float4*>(scene_alloc(s->alloc, n_alloc * sizeof(float4)));
+  d.geo_q = static_cast<float4*>(scene_alloc(s->alloc, n_alloc * sizeof(float4)));
+  d.sh = static_cast<float*>(scene_alloc(s->alloc, sh_floats * sizeof(float)));
+  if (!d.geo_a || !d.geo_b || !d.geo_q || !d.sh) {
+    free_scene(s);
     delete s;
     set_error("adr_create_scene: device allocation failed");
     return ADR_E_OOM;
@@ -105,8 +157,8 @@ extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** o
   adr_status st = ADR_OK;
   if (!desc->pointers_on_device) {
     for (int i = 0; i < 5 && st == ADR_OK; ++i) {
-      if (hipMalloc(&staged[i], counts[i] * sizeof(float)) != hipSuccess) {
-        (void)hipGetLastError();
+      staged[i] = static_cast<float*>(scene_alloc(s->alloc, counts[i] * sizeof(float)));
+      if (!staged[i]) {
         set_error("adr_create_scene: staging allocation failed");
         st = ADR_E_OOM;
       } else if (hipMemcpy(staged[i], src[i], counts[i] * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
@@ -118,13 +170,12 @@ extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** o
     const float* p[5];
     for (int i = 0; i < 5; ++i) p[i] = desc->pointers_on_device ? src[i] : staged[i];
     hipError_t e = launch_pack_scene(*desc, p[0], p[1], p[2], p[3], p[4], d, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) st = hip_fail(e, "pack_scene_kernel");
   }
-  for (int i = 0; i < 5; ++i)
-    if (staged[i]) (void)hipFree(staged[i]);
+  for (int i = 0; i < 5; ++i) scene_free(s->alloc, staged[i], counts[i] * sizeof(float));
   if (st != ADR_OK) {
-    free_scene(d);
+    free_scene(s);
     delete s;
     return st;
   }
@@ -134,7 +185,7 @@ extern "C" adr_status adr_create_scene(const adr_scene_desc* desc, adr_scene** o
 
 extern "C" void adr_destroy_scene(adr_scene* scene) {
   if (!scene) return;
-  free_scene(scene->d);
+  free_scene(scene);
   delete scene;
 }
 

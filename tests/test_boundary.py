@@ -49,17 +49,88 @@ def test_version_string():
 def test_create_scene_rejects_bad_arguments_on_host():
     binding, lib = _lib()
     h = ctypes.c_void_p()
-    assert lib.adr_create_scene(None, ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert lib.adr_create_scene(None, None, ctypes.byref(h)) == binding.ADR_E_INVALID
     assert "NULL" in binding.last_error()
     d = binding.adr_scene_desc()
     d.n, d.sh_degree = 10, 4
-    assert lib.adr_create_scene(ctypes.byref(d), ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert lib.adr_create_scene(ctypes.byref(d), None, ctypes.byref(h)) == binding.ADR_E_INVALID
     assert "sh_degree" in binding.last_error()
     d.sh_degree, d.n = 0, -1
-    assert lib.adr_create_scene(ctypes.byref(d), ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert lib.adr_create_scene(ctypes.byref(d), None, ctypes.byref(h)) == binding.ADR_E_INVALID
     d.n = 5  # NULL arrays with n > 0
-    assert lib.adr_create_scene(ctypes.byref(d), ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert lib.adr_create_scene(ctypes.byref(d), None, ctypes.byref(h)) == binding.ADR_E_INVALID
     assert h.value is None
+
+
+def _fake_desc(binding, n=5, on_device=1, borrow=1, quats=4096):
+    d = binding.adr_scene_desc()
+    d.n, d.sh_degree, d.pointers_on_device, d.borrow = n, 0, on_device, borrow
+    d.means, d.log_scales, d.opacity_logits, d.sh = 1024, 2048, 3072, 5120  # never dereferenced
+    d.quats = quats
+    return d
+
+
+def test_borrowed_scene_needs_aligned_device_pointers():
+    """borrow = 1 keeps the caller's arrays: host pointers, or quaternions not
+    16-byte aligned (read as one 16-byte load), are rejected before any device
+    call."""
+    binding, lib = _lib()
+    h = ctypes.c_void_p()
+    d = _fake_desc(binding, on_device=0)
+    assert lib.adr_create_scene(ctypes.byref(d), None, ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert "device pointers" in binding.last_error()
+    d = _fake_desc(binding, quats=4100)
+    assert lib.adr_create_scene(ctypes.byref(d), None, ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert "aligned" in binding.last_error()
+    assert h.value is None
+
+
+def test_allocator_needs_both_functions():
+    """A caller allocator with alloc but no free (or the reverse) is refused
+    by the scene and the workspace before anything is allocated."""
+    binding, lib = _lib()
+    calls = []
+
+    def _alloc(nbytes, stream, ctx):
+        calls.append(nbytes)
+        return None
+
+    a = binding.adr_allocator()
+    a.alloc = binding.ALLOC_FN(_alloc)  # free left NULL
+    h = ctypes.c_void_p()
+    assert lib.adr_workspace_create(ctypes.byref(a), ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert "alloc and free" in binding.last_error()
+    d = _fake_desc(binding, borrow=0)
+    assert lib.adr_create_scene(ctypes.byref(d), ctypes.byref(a), ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert "alloc and free" in binding.last_error()
+    assert calls == [] and h.value is None
+
+
+def test_workspace_bytes_follow_the_arena_layout():
+    """adr_workspace_bytes is host arithmetic: per Gaussian the 64-byte render
+    record, the 32-byte FP64 record, the 8-byte tile rectangle, three u32
+    arrays and the double-buffered depth keys and ids (16 bytes), plus
+    per-block scan, Preprocess and radix partials; per pair the
+    double-buffered tile ids and Gaussian ids (16 bytes); per tile the ranges
+    (8), the render order (4) and the load partials of four waves (128)."""
+    _, lib = _lib()
+    base = lib.adr_workspace_bytes(0, 0, 0)
+    assert base > 0 and base % 256 == 0
+    n, p, t = 1_000_000, 4_000_000, 8160
+    dg = lib.adr_workspace_bytes(n, 0, 0) - base
+    dp = lib.adr_workspace_bytes(0, p, 0) - base
+    dt = lib.adr_workspace_bytes(0, 0, t) - base
+    assert 132 * n <= dg <= 132.7 * n  # + radix counts, scan and Preprocess partials
+    assert 16 * p <= dp <= 16.3 * p  # + radix counts and chunk starts
+    assert 140 * t <= dt <= 140 * t + 20_000
+    assert lib.adr_workspace_bytes(n, p, t) == base + dg + dp + dt
+    assert lib.adr_workspace_bytes(-1, 0, 0) == -1
+
+
+def test_workspace_reserve_and_capacity_reject_bad_arguments():
+    binding, lib = _lib()
+    assert lib.adr_workspace_reserve(None, 1, 1, 1) == binding.ADR_E_INVALID
+    assert lib.adr_workspace_capacity_bytes(None) == -1
 
 
 def test_render_rejects_bad_arguments_on_host():
@@ -117,8 +188,8 @@ def test_stage_times_and_counters_without_frames():
     _, lib = _lib()
     buf = (ctypes.c_float * 7)()
     assert lib.adr_workspace_stage_times(None, buf, 7) == 0
-    cbuf = (ctypes.c_int64 * 5)()
-    assert lib.adr_workspace_counters(None, cbuf, 5) == 0
+    cbuf = (ctypes.c_int64 * 6)()
+    assert lib.adr_workspace_counters(None, cbuf, 6) == 0
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -144,24 +215,21 @@ def test_server_rejects_bad_arguments_on_host():
     """Serving entry points validate on the host before touching a device."""
     binding, lib = _lib()
     h = ctypes.c_void_p()
-    for n in (0, -1, 65):
-        assert lib.adr_server_create(n, ctypes.byref(h)) == binding.ADR_E_INVALID
-    assert lib.adr_server_create(4, None) == binding.ADR_E_INVALID
+    assert lib.adr_server_create(None, ctypes.byref(h)) == binding.ADR_E_INVALID
+    for slots, batch, budget in ((0, 4, 1 << 30), (65, 4, 1 << 30), (4, 0, 1 << 30), (4, 65, 1 << 30), (4, 4, 0)):
+        cfg = binding.adr_server_config()
+        cfg.n_slots, cfg.max_batch, cfg.memory_budget = slots, batch, budget
+        assert lib.adr_server_create(ctypes.byref(cfg), ctypes.byref(h)) == binding.ADR_E_INVALID
+    assert not h.value
     t = ctypes.c_uint64()
     cam = binding.adr_camera()
     p = binding.RenderParams().to_c()
     f = binding.adr_frame()
-    assert lib.adr_server_submit(None, None, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f),
+    assert lib.adr_server_submit(None, None, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f), 0.0,
                                  ctypes.byref(t)) == binding.ADR_E_INVALID
     fake = ctypes.c_void_p(1)  # never dereferenced: validation fails first
-    assert lib.adr_server_submit(fake, fake, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f),
+    assert lib.adr_server_submit(fake, fake, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f), 0.0,
                                  ctypes.byref(t)) == binding.ADR_E_INVALID  # no image, zero-size camera
     assert lib.adr_server_wait(None, 1, None) == binding.ADR_E_INVALID
+    assert lib.adr_server_stats_get(None, None) == binding.ADR_E_INVALID
     assert lib.adr_clock_s() > 0.0
-
-
-def test_serving_is_switched_off_and_says_so():
-    binding, lib = _lib()
-    h = ctypes.c_void_p()
-    assert lib.adr_server_create(4, ctypes.byref(h)) == binding.ADR_E_UNSUPPORTED
-    assert "switched off" in binding.last_error() and not h.value

@@ -65,6 +65,7 @@ def gpu_frame_once(P, ws, scene_gpu, cam, mode, n_pairs_expected, **kw):
                l_iter=torch.empty((h, w), dtype=torch.int32, device="cuda"),
                l_blend=torch.empty((h, w), dtype=torch.int32, device="cuda"),
                load_sums=torch.zeros(4, dtype=torch.int64, device="cuda"),
+               load_stats=torch.zeros(4, dtype=torch.float64, device="cuda"),
                tiles_touched=torch.empty(max(scene_gpu.n, 1), dtype=torch.int32, device="cuda"),
                keys=torch.empty(cap, dtype=torch.int64, device="cuda"),
                values=torch.empty(cap, dtype=torch.int32, device="cuda"),
@@ -117,6 +118,9 @@ def check_load_sums(g, o):
     li = o["l_iter"].astype(np.int64)
     expect = [lb.sum(), (lb * lb).sum(), li.sum(), (li * li).sum()]
     assert [int(v) for v in g["load_sums"]] == [int(v) for v in expect]
+    if "load_stats" in g:  # Eq. 13, computed in the library from the exact sums
+        want = list(O.load_stats(o["l_blend"])) + list(O.load_stats(o["l_iter"]))
+        np.testing.assert_allclose(g["load_stats"], want, rtol=1e-12, atol=0)
 
 
 @pytest.fixture(scope="module")
@@ -151,6 +155,43 @@ def test_first_frame_on_a_fresh_workspace_matches_the_oracle(P, small, mode):
     check_pixels(g, o)
     check_load_sums(g, o)
     fresh.close()
+
+
+def test_borrowed_scene_and_caller_allocator_give_the_same_frame(P, ws, small):
+    """A scene that reads the caller's row-major device tensors in place
+    (borrow) and a workspace whose arenas come from torch's caching allocator
+    render bitwise the frame of a copied scene on a library workspace."""
+    import torch
+    s, sg, cam = small
+    say("borrowed scene + torch allocator")
+    ref = gpu_frame(P, ws, sg, cam, 2)
+    t = {k: torch.from_numpy(np.ascontiguousarray(getattr(s, k))).cuda()
+         for k in ("means", "log_scales", "quats", "opacity_logits", "sh")}
+    sb = P.Scene(t["means"], t["log_scales"], t["quats"], t["opacity_logits"], t["sh"], s.sh_degree, borrow=True)
+    assert sb.bytes == 0
+    wt = P.Workspace(allocator="torch")
+    g = gpu_frame(P, wt, sb, cam, 2)
+    for k in ("image", "final_t", "l_iter", "l_blend", "load_sums", "load_stats", "keys", "values", "ranges",
+              "tiles_touched"):
+        np.testing.assert_array_equal(g[k], ref[k], err_msg=k)
+    wt.close()
+    sb.close()
+
+
+def test_reserved_workspace_allocates_nothing_while_rendering(P, small):
+    """After adr_workspace_reserve for the frame's sizes, rendering the frame
+    in every cull mode leaves the workspace's device bytes unchanged."""
+    s, sg, cam = small
+    o = O.render_frame(s, cam, oracle_params(0))
+    tiles = ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    r = P.Workspace()
+    r.reserve(s.n, o["n_pairs"], tiles)
+    before = r.capacity_bytes
+    assert before == P.Workspace.bytes_for(s.n, o["n_pairs"], tiles)
+    for mode in (0, 1, 2):
+        gpu_frame(P, r, sg, cam, mode, debug=False)
+    assert r.capacity_bytes == before
+    r.close()
 
 
 @pytest.mark.parametrize("k", [2, 4, 8])
