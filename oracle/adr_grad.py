@@ -118,7 +118,8 @@ def _preprocess(means, log_scales, quats, logits, sh, degree, cam, params: O.Par
     return x, y, conic, opacity, color
 
 
-def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None, dl_dload=None) -> dict:
+def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None, dl_dload=None,
+                tiles=None) -> dict:
     """Gradient of L = sum(dl_dimage * image) + sum(dl_dload * l_blend) with
     respect to the scene inputs, where the per-pixel load l_blend (Eq. 12) is
     taken through the surrogate sum of the blended alphas (slope 1 per blended
@@ -126,8 +127,11 @@ def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None
 
     dl_dimage: (3, H, W). fwd: the forward oracle's render_frame result for the
     same inputs (computed here when absent); its sorted lists, tile ranges and
-    per-pixel l_iter fix the piece. Returns float64 arrays shaped like the
-    scene arrays, plus the loss value.
+    per-pixel l_iter fix the piece. tiles: when given, only these tiles' terms
+    of L are formed; the weights must vanish on every other tile (their terms
+    are then exactly zero, so the gradient is the same), and fwd needs l_iter
+    only there. Returns float64 arrays shaped like the scene arrays, plus the
+    loss value.
     """
     if fwd is None:
         fwd = O.render_frame(scene, cam, params)
@@ -142,8 +146,16 @@ def render_grad(scene, cam, params: O.Params, dl_dimage, fwd: dict | None = None
     ranges = np.asarray(fwd["ranges"], dtype=np.int64)
     l_iter = np.asarray(fwd["l_iter"], dtype=np.int64)
     tx_n, ty_n = O.n_tiles(cam)
+    tile_list = range(tx_n * ty_n) if tiles is None else [int(t) for t in tiles]
+    if tiles is not None:
+        keep = np.zeros((ty_n * O.TILE, tx_n * O.TILE), dtype=bool)
+        for t in tile_list:
+            keep[(t // tx_n) * O.TILE:(t // tx_n + 1) * O.TILE, (t % tx_n) * O.TILE:(t % tx_n + 1) * O.TILE] = True
+        keep = keep[:cam.height, :cam.width]
+        assert not np.any(np.asarray(dl_dimage)[:, ~keep]), "weights outside the given tiles"
+        assert dl_dload is None or not np.any(np.asarray(dl_dload)[~keep]), "load weights outside the given tiles"
     loss = torch.zeros((), dtype=torch.float64)
-    for t in range(tx_n * ty_n):
+    for t in tile_list:
         s, e = int(ranges[t, 0]), int(ranges[t, 1])
         tx, ty = t % tx_n, t // tx_n
         xs = np.arange(tx * O.TILE, min((tx + 1) * O.TILE, cam.width))

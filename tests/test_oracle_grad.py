@@ -120,3 +120,28 @@ def test_load_surrogate_gradient_matches_central_differences():
             fd = (total(perturbed(scene, key, idx, h)) - total(perturbed(scene, key, idx, -h))) / (2 * h)
             an = float(g[key][idx])
             assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (key, idx, fd, an)
+
+
+def test_tile_subset_gives_the_full_gradient_when_other_weights_vanish():
+    """render_grad restricted to some tiles equals the full-frame gradient
+    when the loss weights are zero on every other tile (those tiles' terms
+    are exactly zero), and it refuses weights outside the given tiles."""
+    scene = sh3_scene(120, seed=8)
+    cam = camera_small(64, 48)
+    prm = O.Params(cull=O.CULL_AABB)
+    fwd = O.render_frame(scene, cam, prm)
+    tx_n, ty_n = O.n_tiles(cam)
+    tiles = [1, 5, 6, 10]
+    w = np.zeros((3, cam.height, cam.width))
+    rng = np.random.default_rng(3)
+    for t in tiles:
+        ys = slice((t // tx_n) * 16, (t // tx_n + 1) * 16)
+        xs = slice((t % tx_n) * 16, (t % tx_n + 1) * 16)
+        w[:, ys, xs] = rng.normal(size=w[:, ys, xs].shape)
+    full = G.render_grad(scene, cam, prm, w, fwd)
+    part = G.render_grad(scene, cam, prm, w, fwd, tiles=tiles)
+    for k in KEYS:
+        np.testing.assert_allclose(part[k], full[k], rtol=1e-12, atol=1e-15)
+    assert any(np.abs(full[k]).max() > 0 for k in KEYS)
+    with pytest.raises(AssertionError):
+        G.render_grad(scene, cam, prm, w, fwd, tiles=tiles[:2])
