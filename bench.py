@@ -53,7 +53,10 @@ def parse():
     ap.add_argument("--serve-batch", type=int, default=16, help="frames per batched blend launch")
     ap.add_argument("--serve-budget-gib", type=float, default=24.0,
                     help="device memory admitted requests may reserve (GiB)")
-    ap.add_argument("--cpu-tiles", type=int, default=2048)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="host processes of the CPU baseline (0: min(16, CPUs of the host))")
+    ap.add_argument("--no-lb", action="store_true",
+                    help="skip the load-balancing sweep on the 3M-Gaussian load-imbalanced workload")
     ap.add_argument("--train-iters", type=int, default=600, help="iterations per run of --only train")
     ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb", "seeds"],
                     default=None,
@@ -166,11 +169,16 @@ def main():
     from paper_2409_08669_amd.binding import STAGES
     from synth import scene_clusters, camera_1080p
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    P.load()
     log(f"generating scene: {args.n} Gaussians, SH degree 3, seed {args.seed}")
     scene = scene_clusters(args.n, seed=args.seed)
     cam = camera_1080p()
+    # The CPU baseline first: its worker processes are forked before this
+    # process touches the GPU.
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cam, args.cpu_workers)
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load()
     sg = P.Scene.from_synth(scene)
     ws = P.Workspace()
     w, h = cam.width, cam.height
@@ -229,6 +237,7 @@ def main():
             band_redecisions=counters.get("band_redecisions"), t_replays=counters.get("t_replays"),
             load_mean_blend=mean_b, load_std_blend=std_b, load_mean_iter=mean_i, load_std_iter=std_i)
         images[name] = out["image"].clone()
+        results[name]["fps_two_in_flight"] = two_in_flight(P, sg, cam, params, args.steps, args.warmup, out)
         if name == "aabb":
             # Load imbalance of the paper's pixel-parallel blend: every wave
             # (8 x 8 pixels) runs as long as its longest pixel list, so its
@@ -359,12 +368,13 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                     "algorithmic_bytes": int(b), "avg_ms": round(kern[dom], 4)}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, cam, args.cpu_tiles, n_tiles)
+    lb = None
+    if not args.no_lb:
+        del ws
+        lb = cap_sweep(P, args)
     serving = None
     if args.serve_seconds > 0:
-        del sg, ws, out, images
+        del sg, out, images
         torch.cuda.empty_cache()
         serving = serve_benchmark(P, args)
 
@@ -386,6 +396,7 @@ def main():
                    "n_gaussians": args.n, "width": w, "height": h, "sh_degree": 3, "cull": "aabb",
                    "alpha_low": 1.0 / 255.0, "seed": args.seed},
         "modes": {k: {"fps": round(v["fps"], 2), "ms_per_frame": round(v["ms_per_frame"], 4),
+                      "fps_two_in_flight": round(v["fps_two_in_flight"], 2),
                       "pairs_per_frame": v["pairs"], "stages_ms": {s_: round(x, 4) for s_, x in v["stages_ms"].items()},
                       "load_std_blend": round(v["load_std_blend"], 4), "load_std_iter": round(v["load_std_iter"], 4),
                       "band_redecisions": v["band_redecisions"], "t_replays": v["t_replays"]}
@@ -400,11 +411,36 @@ def main():
         "load_imbalance_E_exec_over_E_alg": results["aabb"].get("load_imbalance_E_exec_over_E_alg"),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "load_balancing": lb,
         "serving_p99_ms": serving["p99_ms"] if serving else None,
         "serving": serving,
         "paper_context": "paper reports ~3.1x over 3DGS (Ours-Full, RTX 3090, trained scenes); AABB alone 1.65-2.11x",
     }
     print(json.dumps(line), flush=True)
+
+
+def two_in_flight(P, sg, cam, params, steps, warmup, like):
+    """Frames/s with two frames in flight: consecutive frames alternate
+    between two workspaces on two streams (default priority), so that one
+    frame's Preprocess, sorts and emission overlap the previous frame's blend.
+    Every frame is still whole; only their overlap differs from the
+    back-to-back figure."""
+    import torch
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    spaces = [P.Workspace(), P.Workspace()]
+    outs = [{k: torch.empty_like(v) for k, v in like.items()} for _ in range(2)]
+    torch.cuda.synchronize()
+    for i in range(warmup + steps):
+        if i == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        k = i % 2
+        P.render(sg, cam, params, spaces[k], **outs[k], stream=streams[k].cuda_stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for w in spaces:
+        w.close()
+    return steps / dt
 
 
 def _ssim(img, ref):
@@ -499,7 +535,8 @@ def cap_sweep(P, args):
     from synth import scene_heavy, cameras_sweep
 
     log("cap sweep: 3M-Gaussian load-imbalanced scene, 32 poses at 1600x1040")
-    sg = P.Scene.from_synth(scene_heavy(3_000_000, seed=args.seed))
+    scene = scene_heavy(3_000_000, seed=args.seed)
+    sg = P.Scene.from_synth(scene)
     cams = cameras_sweep(32)
     ws = P.Workspace()
     w, h = cams[0].width, cams[0].height
@@ -550,9 +587,42 @@ def cap_sweep(P, args):
                              "fps": round(float(np.mean([r[f"kappa{k}"]["fps"] for r in rows])), 2),
                              "std_blend": round(float(np.mean([r[f"kappa{k}"]["std_blend"] for r in rows])), 3),
                              "psnr_db": round(float(np.mean(ps)), 3) if ps else None}
+    oracle_check = cap_oracle_check(P, scene, sg, cams[0], caps, ws, out)
     return {"n_gaussians": 3_000_000, "width": w, "height": h, "poses": len(cams), "frames_per_setting": n_rep,
             "pose0_covered_lblend_mean": round(lb_mean, 3), "pose0_covered_lblend_std": round(lb_std, 3),
-            "caps": caps, "mean": mean, "per_pose": rows}
+            "caps": caps, "mean": mean, "oracle_check_pose0": oracle_check, "per_pose": rows}
+
+
+def cap_oracle_check(P, scene, sg, cam, caps, ws, out, n_tiles_sample=16):
+    """Pose 0 of the load-balancing sweep against the FP64 oracle on seeded
+    tiles: for the exact frame and each cap K, the largest per-channel
+    difference from the oracle run with the same K (the parity bar is 2e-4),
+    and the PSNR of the capped GPU image against the exact oracle image on
+    those tiles (both clipped to [0, 1])."""
+    import numpy as np
+    import oracle as O
+
+    log(f"cap sweep: oracle check of pose 0 on {n_tiles_sample} seeded tiles")
+    params = O.Params(cull=O.CULL_AABB)
+    pre = O.preprocess(scene, cam, params)
+    rects = O.tile_rects(pre, cam, params)
+    keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
+    ranges = O.tile_ranges(keys, cam)
+    tx, ty = O.n_tiles(cam)
+    tiles = np.random.default_rng(17).choice(tx * ty, n_tiles_sample, replace=False)
+    ref = O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+    mask = ref["done"]
+    ref_img = np.clip(ref["image"][:, mask], 0.0, 1.0)
+    res = {"tiles": int(tiles.size), "pixels": int(mask.sum())}
+    for name, k in [("exact", 0)] + [(f"kappa{kk}", caps[kk]) for kk in sorted(caps)]:
+        P.render(sg, cam, P.RenderParams(cull=P.ADR_CULL_AABB, lb_cap=k), ws, **out)
+        g = out["image"].cpu().numpy()[:, mask]
+        o = ref if k == 0 else O.render_image(pre, values, ranges, cam, O.Params(cull=O.CULL_AABB, lb_cap=k),
+                                              tiles=tiles)
+        mse = float(np.mean((np.clip(g, 0.0, 1.0) - ref_img) ** 2))
+        res[name] = {"K": k, "max_abs_diff_vs_same_K_oracle": float(np.abs(g - o["image"][:, mask]).max()),
+                     "psnr_db_vs_exact_oracle": None if mse == 0.0 else round(10.0 * math.log10(1.0 / mse), 3)}
+    return res
 
 
 def train_load_balancing(P, args):
@@ -750,33 +820,77 @@ def serve_benchmark(P, args):
                         "azimuth U[0,360)"}
 
 
-def cpu_baseline(scene, cam, n_tiles_sample, n_tiles):
-    """The FP64 oracle on the host: full preprocess, pair emission and sort of
-    the whole frame, and the blend of a seeded sample of tiles, extrapolated
-    to all tiles."""
+_CPU_STATE = {}
+
+
+def _cpu_tiles(tiles):
+    """Worker: the oracle's blend of a list of tiles (forked: reads the
+    frame's Preprocess and pair lists from the parent's memory)."""
+    import oracle as O
+    st = _CPU_STATE
+    t0 = time.perf_counter()
+    O.render_image(st["pre"], st["values"], st["ranges"], st["cam"], st["params"], tiles=tiles)
+    return time.perf_counter() - t0
+
+
+def _oracle_frame_parallel(scene, cam, params, workers):
+    """One full frame of the FP64 oracle: Preprocess, emission and sort in
+    this process (NumPy, one thread), then the blend of every tile spread over
+    `workers` forked processes (tile rows interleaved so that each worker
+    gets a mix of heavy and light tiles). Returns (seconds, setup seconds)."""
+    import multiprocessing as mp
     import numpy as np
 
     import oracle as O
-
-    log(f"cpu baseline: oracle preprocess + sort of the full frame, blend of {n_tiles_sample} tiles")
-    params = O.Params(cull=O.CULL_AABB)
     t0 = time.perf_counter()
     pre = O.preprocess(scene, cam, params)
     rects = O.tile_rects(pre, cam, params)
     keys, values, _ = O.duplicate_and_sort(pre, rects, cam)
     ranges = O.tile_ranges(keys, cam)
     t1 = time.perf_counter()
-    rng = np.random.default_rng(123)
-    tiles = rng.choice(n_tiles, size=min(n_tiles_sample, n_tiles), replace=False)
-    O.render_image(pre, values, ranges, cam, params, tiles=tiles)
+    _CPU_STATE.update(pre=pre, values=values, ranges=ranges, cam=cam, params=params)
+    tx, ty = O.n_tiles(cam)
+    order = np.argsort(-(ranges[:, 1].astype(np.int64) - ranges[:, 0]), kind="stable")  # longest first
+    chunks = [order[i::workers * 4].tolist() for i in range(workers * 4)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_cpu_tiles, chunks, chunksize=1)
     t2 = time.perf_counter()
-    per_frame = (t1 - t0) + (t2 - t1) * n_tiles / len(tiles)
-    return {"value": round(1.0 / per_frame, 6), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "seconds_per_frame": round(per_frame, 2),
-            "sample": f"FP64 NumPy oracle, one thread: preprocess+emission+sort of all {scene.n} Gaussians "
-                      f"({t1 - t0:.1f} s) and the blend of {len(tiles)} seeded tiles of {n_tiles} "
-                      f"({t2 - t1:.1f} s), blend time extrapolated by tile count",
-            "host_cpus": os.cpu_count()}
+    _CPU_STATE.clear()
+    return t2 - t0, t1 - t0
+
+
+def cpu_baseline(scene, cam, workers):
+    """The FP64 oracle timed on the host's cores: the whole headline frame
+    (AABB culling; every tile blended, nothing extrapolated), and the small
+    parity frame in the three cull modes. Runs before this process touches
+    the GPU, so the forked workers never hold GPU state."""
+    import oracle as O
+    from synth import scene_small, camera_small
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    log(f"cpu baseline: FP64 oracle, whole 1080p frame, {workers} processes")
+    sec, setup = _oracle_frame_parallel(scene, cam, O.Params(cull=O.CULL_AABB), workers)
+    small = {}
+    s1, c1 = scene_small(2000, seed=0), camera_small()
+    for name, mode in (("3sigma", O.CULL_3SIGMA), ("adaptive", O.CULL_ADAPTIVE), ("aabb", O.CULL_AABB)):
+        t, _ = _oracle_frame_parallel(s1, c1, O.Params(cull=mode), workers)
+        small[name] = round(1.0 / t, 3)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    log(f"cpu baseline: {sec:.2f} s per frame ({setup:.2f} s Preprocess + sort in one process)")
+    return {"value": round(1.0 / sec, 5), "unit": "frames/s", "cores": workers, "kind": "oracle",
+            "seconds_per_frame": round(sec, 3),
+            "sample": f"one whole frame of the headline workload (1M Gaussians, SH3, 1920x1080, AABB): FP64 "
+                      f"NumPy oracle, Preprocess + emission + sort in one process ({setup:.1f} s), the blend of "
+                      f"all tiles over {workers} forked processes; nothing extrapolated",
+            "small_frame_fps": {"workload": "2000 Gaussians, SH0, 128x128", **small},
+            "host_cpus": os.cpu_count(), "cpu_model": model}
 
 
 if __name__ == "__main__":
