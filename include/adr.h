@@ -253,6 +253,31 @@ adr_status adr_render_backward_load(const adr_scene* scene, const adr_camera* ca
                                     const adr_frame* fwd, const float* dl_dimage, const float* dl_dload,
                                     adr_scene_grads* grads, adr_workspace* ws, void* stream);
 
+/* adr_render for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, hosts that forbid allocation). Same
+ * arguments, outputs and errors as adr_render, without a workspace: the
+ * frame's workspace is carved from one static device array of
+ * adr_noalloc_scratch_bytes() bytes (256 MiB) that each GPU holds from the
+ * first call on it until the process ends. The call allocates nothing: no
+ * hipMalloc or hipFree, no pinned host memory, no events (so no stage
+ * timing); the pair count comes back by a device-to-host copy and a wait on
+ * the stream. The kernels and their launch configuration are adr_render's,
+ * so the outputs are bitwise the same.
+ * Limits: the per-Gaussian (about 145 bytes each) and per-tile (about 141
+ * bytes each) arrays must fit in the array with room for pairs, else
+ * ADR_E_WORKSPACE before anything is enqueued; the pairs (about 16.5 bytes
+ * each with the sort scratch) take what is left, and a frame with more returns ADR_E_WORKSPACE after
+ * Preprocess with out->n_pairs set (1M Gaussians at 1920 x 1080, ~2.2M
+ * pairs, fit). Every call on a GPU shares that GPU's array: calls are
+ * serialised on the host, but the kernels of a call still running on one
+ * stream race with a later call's on another stream of the same GPU;
+ * synchronise between such calls. Not differentiable (adr_render_backward
+ * needs a workspace). */
+adr_status adr_render_noalloc(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
+                              adr_frame* out, void* stream);
+/* Size in bytes of the static device array adr_render_noalloc carves. */
+int64_t adr_noalloc_scratch_bytes(void);
+
 /* Stage durations (ms) of the last adr_render on ws that had ADR_FLAG_TIMING:
  * [0] preprocess, [1] host wait for the pair count, [2] depth sort of the
  * Gaussians, [3] inclusive sum, [4] duplicate with keys, [5] tile sort of the

@@ -22,5 +22,7 @@ from .binding import (  # noqa: F401
     load,
     render,
     render_frame,
+    render_noalloc,
+    noalloc_scratch_bytes,
     torch_allocator,
 )

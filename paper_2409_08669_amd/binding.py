@@ -40,7 +40,7 @@ EXPORTS = (
     "adr_workspace_capacity_bytes", "adr_render", "adr_render_backward", "adr_render_backward_load",
     "adr_workspace_stage_times", "adr_workspace_counters", "adr_last_error", "adr_version",
     "adr_server_create", "adr_server_destroy", "adr_server_submit", "adr_server_wait", "adr_server_stats_get",
-    "adr_clock_s",
+    "adr_clock_s", "adr_render_noalloc", "adr_noalloc_scratch_bytes",
 )
 
 
@@ -126,6 +126,11 @@ def load(path=None):
     lib.adr_render.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
                                ctypes.POINTER(adr_frame), vp, vp]
     lib.adr_render.restype = i32
+    lib.adr_render_noalloc.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
+                                       ctypes.POINTER(adr_frame), vp]
+    lib.adr_render_noalloc.restype = i32
+    lib.adr_noalloc_scratch_bytes.argtypes = []
+    lib.adr_noalloc_scratch_bytes.restype = i64
     lib.adr_render_backward.argtypes = [vp, ctypes.POINTER(adr_camera), ctypes.POINTER(adr_render_params),
                                         ctypes.POINTER(adr_frame), vp, ctypes.POINTER(adr_scene_grads), vp, vp]
     lib.adr_render_backward.restype = i32
@@ -362,6 +367,25 @@ def _ptr(t):
     return 0 if t is None else int(t.data_ptr())
 
 
+def _frame(image, final_t, l_iter, l_blend, load_sums, load_stats, tiles_touched, keys, values, ranges,
+           pair_capacity) -> adr_frame:
+    f = adr_frame()
+    f.image, f.final_t, f.l_iter, f.l_blend = _ptr(image), _ptr(final_t), _ptr(l_iter), _ptr(l_blend)
+    f.load_sums, f.load_stats, f.tiles_touched = _ptr(load_sums), _ptr(load_stats), _ptr(tiles_touched)
+    f.keys, f.values, f.ranges = _ptr(keys), _ptr(values), _ptr(ranges)
+    f.pair_capacity = int(pair_capacity)
+    return f
+
+
+def _finish(st: int, f: adr_frame) -> int:
+    if st == ADR_E_WORKSPACE:
+        e = AdrError(st, last_error())
+        e.n_pairs = int(f.n_pairs)
+        raise e
+    _check(st)
+    return int(f.n_pairs)
+
+
 def render(scene: Scene, cam, params: RenderParams, ws: Workspace, image, final_t=None, l_iter=None,
            l_blend=None, load_sums=None, load_stats=None, tiles_touched=None, keys=None, values=None, ranges=None,
            pair_capacity: int = 0, stream=None) -> int:
@@ -370,23 +394,39 @@ def render(scene: Scene, cam, params: RenderParams, ws: Workspace, image, final_
     import torch
 
     lib = load()
-    f = adr_frame()
-    f.image, f.final_t, f.l_iter, f.l_blend = _ptr(image), _ptr(final_t), _ptr(l_iter), _ptr(l_blend)
-    f.load_sums, f.load_stats, f.tiles_touched = _ptr(load_sums), _ptr(load_stats), _ptr(tiles_touched)
-    f.keys, f.values, f.ranges = _ptr(keys), _ptr(values), _ptr(ranges)
-    f.pair_capacity = int(pair_capacity)
+    f = _frame(image, final_t, l_iter, l_blend, load_sums, load_stats, tiles_touched, keys, values, ranges,
+               pair_capacity)
     c = camera_to_c(cam)
     p = params.to_c()
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     st = lib.adr_render(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f), ws.handle,
                         ctypes.c_void_p(int(stream)))
-    if st == ADR_E_WORKSPACE:
-        e = AdrError(st, last_error())
-        e.n_pairs = int(f.n_pairs)
-        raise e
-    _check(st)
-    return int(f.n_pairs)
+    return _finish(st, f)
+
+
+def render_noalloc(scene: Scene, cam, params: RenderParams, image, final_t=None, l_iter=None, l_blend=None,
+                   load_sums=None, load_stats=None, tiles_touched=None, keys=None, values=None, ranges=None,
+                   pair_capacity: int = 0, stream=None) -> int:
+    """adr_render_noalloc (no workspace; the library's fixed device scratch)
+    into caller-allocated device tensors; returns the pair count. Raises
+    AdrError on any non-OK status (ADR_E_WORKSPACE carries n_pairs)."""
+    import torch
+
+    lib = load()
+    f = _frame(image, final_t, l_iter, l_blend, load_sums, load_stats, tiles_touched, keys, values, ranges,
+               pair_capacity)
+    c = camera_to_c(cam)
+    p = params.to_c()
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    st = lib.adr_render_noalloc(scene.handle, ctypes.byref(c), ctypes.byref(p), ctypes.byref(f),
+                                ctypes.c_void_p(int(stream)))
+    return _finish(st, f)
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load().adr_noalloc_scratch_bytes())
 
 
 def render_frame(scene: Scene, cam, params: RenderParams, ws: Workspace = None, debug: bool = False,

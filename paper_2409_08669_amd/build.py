@@ -14,7 +14,8 @@ import sys
 PKG = pathlib.Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libadr.so"
-SOURCES = ["api.hip", "scene.hip", "preprocess.hip", "scan.hip", "emit.hip", "sort.hip", "render.hip", "server.hip"]
+SOURCES = ["api.hip", "scene.hip", "preprocess.hip", "scan.hip", "emit.hip", "sort.hip", "render.hip", "server.hip",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -168,6 +168,35 @@ def test_render_rejects_bad_arguments_on_host():
         binding.ADR_E_INVALID
 
 
+def test_noalloc_render_rejects_bad_arguments_on_host():
+    """adr_render_noalloc validates like adr_render before it looks up its
+    device scratch: NULL handles, a missing image, bad camera and params."""
+    binding, lib = _lib()
+    assert lib.adr_noalloc_scratch_bytes() == 256 << 20
+    cam = binding.adr_camera()
+    cam.fx = cam.fy = 100.0
+    cam.width = cam.height = 64
+    cam.cx = cam.cy = 32.0
+    cam.near_z = 0.2
+    p = binding.RenderParams().to_c()
+    f = binding.adr_frame()
+    assert lib.adr_render_noalloc(None, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f), None) == \
+        binding.ADR_E_INVALID
+    fake = ctypes.c_void_p(1)  # never dereferenced: validation fails first
+    assert lib.adr_render_noalloc(fake, ctypes.byref(cam), ctypes.byref(p), ctypes.byref(f), None) == \
+        binding.ADR_E_INVALID
+    assert "image" in binding.last_error()
+    f.image = 1
+    c2 = binding.adr_camera.from_buffer_copy(cam)
+    c2.width = 0
+    assert lib.adr_render_noalloc(fake, ctypes.byref(c2), ctypes.byref(p), ctypes.byref(f), None) == \
+        binding.ADR_E_INVALID
+    p2 = binding.RenderParams().to_c()
+    p2.alpha_low = 0.0
+    assert lib.adr_render_noalloc(fake, ctypes.byref(cam), ctypes.byref(p2), ctypes.byref(f), None) == \
+        binding.ADR_E_INVALID
+
+
 def test_backward_rejects_missing_arguments_on_the_host():
     """adr_render_backward checks its arguments before touching the device:
     NULL handles, and a forward frame without final_t or l_iter."""
