@@ -464,7 +464,13 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     Src src, int64_t n, ShConsts shc, CamArgs cam, double lowpass,
     const float* __restrict__ grad2d, float* __restrict__ d_means, float* __restrict__ d_log_scales,
     float* __restrict__ d_quats, float* __restrict__ d_logits, float* __restrict__ d_sh) {
-  using real = float;  // gradients need ~1e-4 relative accuracy: FP32 throughout
+  // The colour part is FP32. The covariance part (Sigma, Sigma', its inverse
+  // and the chain back to scales, rotation and centre) is FP64: for an
+  // elongated Gaussian the gradient along its long axis is a small
+  // difference of large terms of dL/dSigma', which FP32 resolves only to a
+  // few percent (axis ratio ~100).
+  using real = float;
+  using dreal = double;
   const real cfx = (real)cam.fx, cfy = (real)cam.fy, clim_x = (real)cam.lim_x, clim_y = (real)cam.lim_y;
   const real ct[3] = {(real)cam.t[0], (real)cam.t[1], (real)cam.t[2]};
   const real cpos[3] = {(real)cam.cam_pos[0], (real)cam.cam_pos[1], (real)cam.cam_pos[2]};
@@ -487,41 +493,47 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
   const real px = W[0] * mx + W[1] * my + W[2] * mz + ct[0];
   const real py = W[3] * mx + W[4] * my + W[5] * mz + ct[1];
   const real pz = W[6] * mx + W[7] * my + W[8] * mz + ct[2];
-  real dm[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dlogit = 0;
+  dreal dm[3] = {0, 0, 0}, dls[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0};
+  real dlogit = 0;
   bool live = pz > (real)cam.near_z;
   // forward, as in Preprocess
-  const real sc[3] = {exp((real)gb.x), exp((real)gb.y), exp((real)gb.z)};
-  const real qn2 = (real)gq.x * gq.x + (real)gq.y * gq.y + (real)gq.z * gq.z + (real)gq.w * gq.w;
-  const real qn = 1.0f / sqrt(qn2);
-  const real qw = gq.x * qn, qx = gq.y * qn, qy = gq.z * qn, qz = gq.w * qn;
-  real R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+  const dreal sc[3] = {exp((real)gb.x), exp((real)gb.y), exp((real)gb.z)};
+  const dreal qn2 = (dreal)gq.x * gq.x + (dreal)gq.y * gq.y + (dreal)gq.z * gq.z + (dreal)gq.w * gq.w;
+  const dreal qn = 1.0 / sqrt(qn2);
+  const dreal qw = gq.x * qn, qx = gq.y * qn, qy = gq.z * qn, qz = gq.w * qn;
+  const dreal R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
                     {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
                     {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-  real M[3][3], Sg[3][3];
+  dreal M[3][3], Sg[3][3];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sc[j];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) Sg[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
-  const real z = live ? pz : 1.0f;
-  const real rx = px / z, ry = py / z;
+  const real zf = live ? pz : 1.0f;
+  const real rx = px / zf, ry = py / zf;
+  const dreal z = zf;
   const bool cx_free = rx > -clim_x && rx < clim_x, cy_free = ry > -clim_y && ry < clim_y;
-  const real xt = z * fmin(fmax(rx, -clim_x), clim_x);
-  const real yt = z * fmin(fmax(ry, -clim_y), clim_y);
-  const real j00 = cfx / z, j02 = -cfx * xt / (z * z);
-  const real j11 = cfy / z, j12 = -cfy * yt / (z * z);
-  real T[2][3];
+  const dreal xt = z * (dreal)fmin(fmax(rx, -clim_x), clim_x);
+  const dreal yt = z * (dreal)fmin(fmax(ry, -clim_y), clim_y);
+  const dreal dfx = cam.fx, dfy = cam.fy;
+  const dreal j00 = dfx / z, j02 = -dfx * xt / (z * z);
+  const dreal j11 = dfy / z, j12 = -dfy * yt / (z * z);
+  dreal Wd[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) Wd[i] = cam.r[i];
+  dreal T[2][3];
   for (int k = 0; k < 3; ++k) {
-    T[0][k] = j00 * W[k] + j02 * W[6 + k];
-    T[1][k] = j11 * W[3 + k] + j12 * W[6 + k];
+    T[0][k] = j00 * Wd[k] + j02 * Wd[6 + k];
+    T[1][k] = j11 * Wd[3 + k] + j12 * Wd[6 + k];
   }
-  real TS[2][3];  // T Sigma
+  dreal TS[2][3];  // T Sigma
   for (int i = 0; i < 2; ++i)
     for (int k = 0; k < 3; ++k) TS[i][k] = T[i][0] * Sg[0][k] + T[i][1] * Sg[1][k] + T[i][2] * Sg[2][k];
-  const real a = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + lp;
-  const real b = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
-  const real c = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + lp;
-  const real det = a * c - b * b;
-  live = live && det > 0.0f;
+  const dreal a = TS[0][0] * T[0][0] + TS[0][1] * T[0][1] + TS[0][2] * T[0][2] + lowpass;
+  const dreal b = TS[0][0] * T[1][0] + TS[0][1] * T[1][1] + TS[0][2] * T[1][2];
+  const dreal c = TS[1][0] * T[1][0] + TS[1][1] * T[1][1] + TS[1][2] * T[1][2] + lowpass;
+  const dreal det = a * c - b * b;
+  live = live && det > 0.0;
   if (live) {
     const float* gr = grad2d + g * kGrad2d;
     const real gx = gr[0], gy = gr[1], gA = gr[2], gB = gr[3], gC = gr[4], gO = gr[5];
@@ -628,68 +640,69 @@ __global__ void __launch_bounds__(256) preprocess_backward_kernel(
     dm[1] += (dv[1] - vdot * vy) / vlen;
     dm[2] += (dv[2] - vdot * vz) / vlen;
     // conic N = M^-1: dM = -N dN N, with dN = [[gA, gB/2], [gB/2, gC]]
-    const real NA = c / det, NB = -b / det, NC = a / det;
-    const real P00 = NA * gA + NB * 0.5f * gB, P01 = NA * 0.5f * gB + NB * gC;
-    const real P10 = NB * gA + NC * 0.5f * gB, P11 = NB * 0.5f * gB + NC * gC;
-    const real da = -(P00 * NA + P01 * NB);
-    const real db = -2.0f * (P00 * NB + P01 * NC);
-    const real dc = -(P10 * NB + P11 * NC);
+    const dreal NA = c / det, NB = -b / det, NC = a / det;
+    const dreal P00 = NA * gA + NB * 0.5 * gB, P01 = NA * 0.5 * gB + NB * gC;
+    const dreal P10 = NB * gA + NC * 0.5 * gB, P11 = NB * 0.5 * gB + NC * gC;
+    const dreal da = -(P00 * NA + P01 * NB);
+    const dreal db = -2.0 * (P00 * NB + P01 * NC);
+    const dreal dc = -(P10 * NB + P11 * NC);
     // Sigma' = T Sigma T^T: G = [[da, db/2], [db/2, dc]]
-    const real G[2][2] = {{da, 0.5f * db}, {0.5f * db, dc}};
-    real dS[3][3], dT[2][3];
+    const dreal G[2][2] = {{da, 0.5 * db}, {0.5 * db, dc}};
+    dreal dS[3][3], dT[2][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        real acc = 0.0f;
+        dreal acc = 0.0;
         for (int u = 0; u < 2; ++u)
           for (int v = 0; v < 2; ++v) acc += T[u][i] * G[u][v] * T[v][j];
         dS[i][j] = acc;
       }
     for (int u = 0; u < 2; ++u)
-      for (int k = 0; k < 3; ++k) dT[u][k] = 2.0f * (G[u][0] * TS[0][k] + G[u][1] * TS[1][k]);
+      for (int k = 0; k < 3; ++k) dT[u][k] = 2.0 * (G[u][0] * TS[0][k] + G[u][1] * TS[1][k]);
     // T = J W
-    const real dj00 = dT[0][0] * W[0] + dT[0][1] * W[1] + dT[0][2] * W[2];
-    const real dj02 = dT[0][0] * W[6] + dT[0][1] * W[7] + dT[0][2] * W[8];
-    const real dj11 = dT[1][0] * W[3] + dT[1][1] * W[4] + dT[1][2] * W[5];
-    const real dj12 = dT[1][0] * W[6] + dT[1][1] * W[7] + dT[1][2] * W[8];
-    real dpx = 0.0f, dpy = 0.0f, dpz = 0.0f;
-    dpz += -dj00 * cfx / (z * z) - dj11 * cfy / (z * z);
+    const dreal dj00 = dT[0][0] * Wd[0] + dT[0][1] * Wd[1] + dT[0][2] * Wd[2];
+    const dreal dj02 = dT[0][0] * Wd[6] + dT[0][1] * Wd[7] + dT[0][2] * Wd[8];
+    const dreal dj11 = dT[1][0] * Wd[3] + dT[1][1] * Wd[4] + dT[1][2] * Wd[5];
+    const dreal dj12 = dT[1][0] * Wd[6] + dT[1][1] * Wd[7] + dT[1][2] * Wd[8];
+    const dreal dpx_ = px, dpy_ = py;
+    dreal dpx = 0.0, dpy = 0.0, dpz = 0.0;
+    dpz += -dj00 * dfx / (z * z) - dj11 * dfy / (z * z);
     if (cx_free) {  // j02 = -fx px / z^2
-      dpx += -dj02 * cfx / (z * z);
-      dpz += dj02 * 2.0f * cfx * px / (z * z * z);
+      dpx += -dj02 * dfx / (z * z);
+      dpz += dj02 * 2.0 * dfx * dpx_ / (z * z * z);
     } else {  // j02 = -fx L / z, L = +-lim_x
-      dpz += dj02 * cfx * (xt / z) / (z * z);
+      dpz += dj02 * dfx * (xt / z) / (z * z);
     }
     if (cy_free) {
-      dpy += -dj12 * cfy / (z * z);
-      dpz += dj12 * 2.0f * cfy * py / (z * z * z);
+      dpy += -dj12 * dfy / (z * z);
+      dpz += dj12 * 2.0 * dfy * dpy_ / (z * z * z);
     } else {
-      dpz += dj12 * cfy * (yt / z) / (z * z);
+      dpz += dj12 * dfy * (yt / z) / (z * z);
     }
     // projected centre
-    dpx += gx * cfx / z;
-    dpy += gy * cfy / z;
-    dpz += -gx * cfx * px / (z * z) - gy * cfy * py / (z * z);
+    dpx += gx * dfx / z;
+    dpy += gy * dfy / z;
+    dpz += -gx * dfx * dpx_ / (z * z) - gy * dfy * dpy_ / (z * z);
     // p = W mean + t
-    dm[0] += W[0] * dpx + W[3] * dpy + W[6] * dpz;
-    dm[1] += W[1] * dpx + W[4] * dpy + W[7] * dpz;
-    dm[2] += W[2] * dpx + W[5] * dpy + W[8] * dpz;
+    dm[0] += Wd[0] * dpx + Wd[3] * dpy + Wd[6] * dpz;
+    dm[1] += Wd[1] * dpx + Wd[4] * dpy + Wd[7] * dpz;
+    dm[2] += Wd[2] * dpx + Wd[5] * dpy + Wd[8] * dpz;
     // Sigma = M M^T: dM = 2 dS M; M = R diag(s)
-    real dR[3][3];
+    dreal dR[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        const real dMij = 2.0f * (dS[i][0] * M[0][j] + dS[i][1] * M[1][j] + dS[i][2] * M[2][j]);
+        const dreal dMij = 2.0 * (dS[i][0] * M[0][j] + dS[i][1] * M[1][j] + dS[i][2] * M[2][j]);
         dR[i][j] = dMij * sc[j];
         dls[j] += dMij * R[i][j] * sc[j];
       }
     // R(q_hat), q_hat = q / |q|
-    const real dw = 2 * (-qz * dR[0][1] + qy * dR[0][2] + qz * dR[1][0] - qx * dR[1][2] - qy * dR[2][0] + qx * dR[2][1]);
-    const real dx_ = 2 * (qy * dR[0][1] + qz * dR[0][2] + qy * dR[1][0] - 2 * qx * dR[1][1] - qw * dR[1][2] +
+    const dreal dw = 2 * (-qz * dR[0][1] + qy * dR[0][2] + qz * dR[1][0] - qx * dR[1][2] - qy * dR[2][0] + qx * dR[2][1]);
+    const dreal dx_ = 2 * (qy * dR[0][1] + qz * dR[0][2] + qy * dR[1][0] - 2 * qx * dR[1][1] - qw * dR[1][2] +
                             qz * dR[2][0] + qw * dR[2][1] - 2 * qx * dR[2][2]);
-    const real dy_ = 2 * (-2 * qy * dR[0][0] + qx * dR[0][1] + qw * dR[0][2] + qx * dR[1][0] + qz * dR[1][2] -
+    const dreal dy_ = 2 * (-2 * qy * dR[0][0] + qx * dR[0][1] + qw * dR[0][2] + qx * dR[1][0] + qz * dR[1][2] -
                             qw * dR[2][0] + qz * dR[2][1] - 2 * qy * dR[2][2]);
-    const real dz_ = 2 * (-2 * qz * dR[0][0] - qw * dR[0][1] + qx * dR[0][2] + qw * dR[1][0] - 2 * qz * dR[1][1] +
+    const dreal dz_ = 2 * (-2 * qz * dR[0][0] - qw * dR[0][1] + qx * dR[0][2] + qw * dR[1][0] - 2 * qz * dR[1][1] +
                             qy * dR[1][2] + qx * dR[2][0] + qy * dR[2][1]);
-    const real dotq = dw * qw + dx_ * qx + dy_ * qy + dz_ * qz;
+    const dreal dotq = dw * qw + dx_ * qx + dy_ * qy + dz_ * qz;
     dq[0] = (dw - dotq * qw) * qn;
     dq[1] = (dx_ - dotq * qx) * qn;
     dq[2] = (dy_ - dotq * qy) * qn;
