@@ -15,7 +15,7 @@
 //
 // Each pass is reduce-then-scan: per-workgroup digit counts, one workgroup
 // per digit scans them into scatter offsets, and a downsweep ranks the
-// workgroup's 2048 or 4096 keys in LDS and scatters them. Ranking is stable and uses wave64
+// workgroup's 2048, 4096 or 8192 keys in LDS and scatters them. Ranking is stable and uses wave64
 // ballots: the lanes of a row that share a digit are found with eight
 // ballots, one per digit bit, and counted with popcounts, so no atomics decide
 // an order. (A single-launch decoupled look-back was tried first; its chain of
@@ -26,13 +26,19 @@ namespace adr {
 
 namespace {
 
-constexpr int kThreads = 256;
-// Keys per lane: 8 (2048 per workgroup) up to 1.5M keys, so that a million
-// depth keys still give every CU a few workgroups; 16 (4096) above that.
-constexpr int kSmallSortItems = 8, kLargeSortItems = 16;
-constexpr int64_t kSmallSortMax = 1536 * 1024;
+// Eight waves per workgroup. Keys per lane: 4 (2048 per workgroup) up to
+// 1.5M keys, so that a million depth keys still give every CU a few
+// workgroups; 8 (4096) up to 3M; 16 (8192) above. Larger workgroups make
+// each digit's run in the output longer, so the scattered stores fill more
+// of each cache line.
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr int kSmallSortItems = 4, kMidSortItems = 8, kLargeSortItems = 16;
+constexpr int64_t kSmallSortMax = 1536 * 1024, kMidSortMax = 3 * 1024 * 1024;
 
-__host__ __device__ constexpr int sort_items(int64_t n) { return n <= kSmallSortMax ? kSmallSortItems : kLargeSortItems; }
+__host__ __device__ constexpr int sort_items(int64_t n) {
+  return n <= kSmallSortMax ? kSmallSortItems : n <= kMidSortMax ? kMidSortItems : kLargeSortItems;
+}
 constexpr int kRadix = 256;
 constexpr int kMaxPasses = 4;
 
@@ -70,9 +76,9 @@ __device__ __forceinline__ uint32_t digit_of(uint32_t k, KeyMap km, int shift) {
 template <int kItems>
 __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __restrict__ kin, int64_t n, int shift,
                                                            KeyMap km, uint32_t* __restrict__ counts, int64_t nb) {
-  __shared__ uint32_t wh[4][kRadix];
+  __shared__ uint32_t wh[kWaves][kRadix];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int i = tid; i < 4 * kRadix; i += kThreads) (&wh[0][0])[i] = 0u;
+  for (int i = tid; i < kWaves * kRadix; i += kThreads) (&wh[0][0])[i] = 0u;
   __syncthreads();
   constexpr int kTileKeys = kThreads * kItems;
   const int64_t wave_base = (int64_t)blockIdx.x * kTileKeys + (int64_t)wid * (kItems * 64);
@@ -82,7 +88,12 @@ __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __res
     if (idx < n) atomicAdd(&wh[wid][digit_of(kin[idx], km, shift)], 1u);
   }
   __syncthreads();
-  counts[(int64_t)tid * nb + blockIdx.x] = wh[0][tid] + wh[1][tid] + wh[2][tid] + wh[3][tid];
+  if (tid < kRadix) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) c += wh[w][tid];
+    counts[(int64_t)tid * nb + blockIdx.x] = c;
+  }
 }
 
 // One workgroup per digit d: counts[d * nb + b] becomes the number of keys
@@ -91,7 +102,7 @@ __global__ void __launch_bounds__(kThreads) upsweep_kernel(const uint32_t* __res
 // waits for another and no global atomics are needed.)
 __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __restrict__ counts, int64_t nb,
                                                                  uint32_t* __restrict__ totals) {
-  __shared__ uint32_t scan_tmp[4];
+  __shared__ uint32_t scan_tmp[kWaves];
   __shared__ uint32_t s_last;
   const int d = blockIdx.x;
   uint32_t carry = 0;
@@ -109,7 +120,7 @@ __global__ void __launch_bounds__(kThreads) digit_offsets_kernel(uint32_t* __res
   if (threadIdx.x == 0) totals[d] = carry;
 }
 
-// Stable rank of the workgroup's 4096 keys and scatter to the offsets of the
+// Stable rank of the workgroup's keys and scatter to the offsets of the
 // pass.
 template <int kItems>
 __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __restrict__ kin,
@@ -124,17 +135,20 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   constexpr int kTileKeys = kThreads * kItems;
   __shared__ uint32_t skeys[kTileKeys];
   __shared__ uint32_t svals[kTileKeys];
-  __shared__ uint32_t wcnt[4][kRadix];
+  __shared__ uint32_t wcnt[kWaves][kRadix];
   __shared__ uint32_t blk_start[kRadix];
   __shared__ uint32_t glob_base[kRadix];
-  __shared__ uint32_t scan_tmp[4];
+  __shared__ uint32_t scan_tmp[kWaves];
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const uint32_t bid = blockIdx.x;
-  for (int i = tid; i < 4 * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0u;
+  for (int i = tid; i < kWaves * kRadix; i += kThreads) (&wcnt[0][0])[i] = 0u;
   // start of digit tid's run in the output: keys with a smaller digit, plus
   // keys with this digit in earlier workgroups
-  glob_base[tid] = block_excl_scan(totals[tid], scan_tmp) + offsets[(int64_t)tid * nb + bid];
+  {
+    const uint32_t gb = block_excl_scan(tid < kRadix ? totals[tid] : 0u, scan_tmp);
+    if (tid < kRadix) glob_base[tid] = gb + offsets[(int64_t)tid * nb + bid];
+  }
   __syncthreads();
   const int64_t wave_base = (int64_t)bid * kTileKeys + (int64_t)wid * (kItems * 64);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -171,14 +185,21 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   }
   __syncthreads();
 
-  // Per digit: offsets of the four waves and the workgroup's digit starts.
+  // Per digit: offsets of the waves and the workgroup's digit starts.
   const int d = tid;
-  const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
-  wcnt[0][d] = 0u;
-  wcnt[1][d] = c0;
-  wcnt[2][d] = c0 + c1;
-  wcnt[3][d] = c0 + c1 + c2;
-  blk_start[d] = block_excl_scan(c0 + c1 + c2 + c3, scan_tmp);
+  uint32_t dsum = 0;
+  if (d < kRadix) {
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wcnt[w][d];
+      wcnt[w][d] = dsum;
+      dsum += c;
+    }
+  }
+  {
+    const uint32_t bs = block_excl_scan(dsum, scan_tmp);
+    if (d < kRadix) blk_start[d] = bs;
+  }
   // The scan's own barriers come before this write, and the placement below
   // reads the starts of digits that other waves own: a barrier of its own.
   __syncthreads();
@@ -219,6 +240,18 @@ __global__ void __launch_bounds__(kThreads) downsweep_kernel(const uint32_t* __r
   }
 }
 
+// One 8-bit pass: digit counts per workgroup, their scan, the downsweep.
+template <int kItems>
+void sort_pass(uint32_t* keys[2], uint32_t* vals[2], int cur, int64_t n, int p, KeyMap km, uint32_t* counts,
+               int64_t nb, uint32_t* totals, const uint32_t* gs, uint32_t* gd, int64_t gather_n,
+               unsigned long long* bad_count, hipStream_t stream) {
+  upsweep_kernel<kItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
+  digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
+  downsweep_kernel<kItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], vals[cur], keys[cur ^ 1],
+                                                                       vals[cur ^ 1], n, 8 * p, km, counts, nb, totals,
+                                                                       gs, gd, (uint32_t)gather_n, bad_count);
+}
+
 }  // namespace
 
 int64_t sort_scratch_entries(int64_t n) {
@@ -253,19 +286,12 @@ hipError_t launch_radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t n, in
     const bool last = p == n_pass - 1;
     const uint32_t* gs = last ? gather_src : nullptr;
     uint32_t* gd = last ? gather_dst : nullptr;
-    if (items == kSmallSortItems) {
-      upsweep_kernel<kSmallSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
-      digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
-      downsweep_kernel<kSmallSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd, (uint32_t)gather_n,
-          bad_count);
-    } else {
-      upsweep_kernel<kLargeSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(keys[cur], n, 8 * p, km, counts, nb);
-      digit_offsets_kernel<<<dim3(kRadix), kThreads, 0, stream>>>(counts, nb, totals);
-      downsweep_kernel<kLargeSortItems><<<dim3((unsigned)nb), kThreads, 0, stream>>>(
-          keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], n, 8 * p, km, counts, nb, totals, gs, gd, (uint32_t)gather_n,
-          bad_count);
-    }
+    if (items == kSmallSortItems)
+      sort_pass<kSmallSortItems>(keys, vals, cur, n, p, km, counts, nb, totals, gs, gd, gather_n, bad_count, stream);
+    else if (items == kMidSortItems)
+      sort_pass<kMidSortItems>(keys, vals, cur, n, p, km, counts, nb, totals, gs, gd, gather_n, bad_count, stream);
+    else
+      sort_pass<kLargeSortItems>(keys, vals, cur, n, p, km, counts, nb, totals, gs, gd, gather_n, bad_count, stream);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     cur ^= 1;
   }
