@@ -192,7 +192,18 @@ int64_t adr_scene_size(const adr_scene* scene);
 /* Device bytes the scene holds (0 for a borrowed scene). */
 int64_t adr_scene_bytes(const adr_scene* scene);
 
-/* Creates an empty workspace on the current device. allocator (may be NULL)
+/* Creates an empty workspace on the current device. It holds two frame
+ * slots that consecutive adr_render calls alternate between, and a side
+ * stream (default priority): for a scene that is not borrowed, a frame's
+ * stages up to the tile order run on the side stream, which waits only for
+ * the previous frame of the same slot (its blend, copies and any backward),
+ * not for the caller's stream, so they overlap the previous frame's blend;
+ * the blend and everything after it run on the caller's stream after the
+ * side stream's part. Outputs are only written on the caller's stream, and
+ * an owned scene is immutable, so every frame's results are as if all of it
+ * ran on the caller's stream. A borrowed scene runs every stage on the
+ * caller's stream (the caller may change its arrays between frames).
+ * allocator (may be NULL)
  * provides its arenas and must stay valid until adr_workspace_destroy. With
  * a caller allocator an arena that is too small for a frame is replaced
  * inside adr_render (alloc the new one, stream-ordered free of the old one).
@@ -204,15 +215,16 @@ int64_t adr_scene_bytes(const adr_scene* scene);
 adr_status adr_workspace_create(const adr_allocator* allocator, adr_workspace** out);
 /* Waits for the device, then releases every arena. */
 void adr_workspace_destroy(adr_workspace* ws);
-/* Grows the arenas (never shrinks them) to hold a frame of n_gauss
- * Gaussians, n_pairs Gaussian-tile pairs and n_tiles tiles, and frees the
- * arenas kept from earlier growth. Synchronises the device. A render that
- * stays within the reserved sizes allocates nothing. */
+/* Grows the arenas of both frame slots (never shrinks them) to hold a
+ * frame of n_gauss Gaussians, n_pairs Gaussian-tile pairs and n_tiles tiles,
+ * and frees the arenas kept from earlier growth. Synchronises the device. A
+ * render that stays within the reserved sizes allocates nothing. */
 adr_status adr_workspace_reserve(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles);
-/* Device bytes a workspace needs for such a frame (arena sizes, without
- * growth headroom); -1 for negative arguments. Host arithmetic only. */
+/* Device bytes one frame slot needs for such a frame (arena sizes, without
+ * growth headroom); -1 for negative arguments. Host arithmetic only. A
+ * workspace reserved for the frame holds twice this (two slots). */
 int64_t adr_workspace_bytes(int64_t n_gauss, int64_t n_pairs, int64_t n_tiles);
-/* Device bytes the workspace's arenas hold now, kept arenas included. */
+/* Device bytes the arenas of both slots hold now, kept arenas included. */
 int64_t adr_workspace_capacity_bytes(const adr_workspace* ws);
 
 /* Renders one frame: Preprocess (projection, SH colour, cull per params.cull),
@@ -282,7 +294,9 @@ int64_t adr_noalloc_scratch_bytes(void);
  * [0] preprocess, [1] host wait for the pair count, [2] depth sort of the
  * Gaussians, [3] inclusive sum, [4] duplicate with keys, [5] tile sort of the
  * pairs, [6] tile ranges, [7] tile render order, [8] render (the blend kernel
- * alone), [9] load-sum reduction.
+ * alone, from its own start: on a pipelined workspace the stages before it
+ * run on the workspace's side stream and may end before the previous frame's
+ * blend does), [9] load-sum reduction.
  * Waits for the frame to finish. Returns the number of stages written. */
 int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
 

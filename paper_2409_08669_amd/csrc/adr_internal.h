@@ -210,7 +210,9 @@ struct adr_workspace {
   unsigned long long* notify_host = nullptr;
   unsigned long long* notify_dev = nullptr;
   unsigned long long frame_seq = 0;
-  static constexpr int kEvents = 11;
+  // ev[0..10]: the stage boundaries of a timed frame; ev[11]: the blend's start
+  // on the caller's stream (after any wait for the previous frame)
+  static constexpr int kEvents = 12;
   hipEvent_t ev[kEvents] = {};
   bool timing_valid = false;
   hipStream_t last_stream = nullptr;
@@ -222,6 +224,18 @@ struct adr_workspace {
   adr_camera last_cam{};
   adr_render_params last_params{};
   const uint32_t* last_vals = nullptr;  // its sorted Gaussian ids
+  // A pipelined workspace (adr_workspace_create) has two frame slots: this
+  // handle (slot 0), which owns slot 1 (twin) and the side stream, and the
+  // twin. A frame of an owned scene runs its stages up to the tile order on
+  // the side stream, which waits only for the previous frame of the same
+  // slot, so they overlap the blend of the frame before on the caller's
+  // stream. Both slots have their own arenas, events and pinned words.
+  adr_workspace* twin = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t prep_done = nullptr;     // the slot's stages up to the tile order (side stream)
+  hipEvent_t slot_free = nullptr;     // the slot's last frame or backward (caller's stream)
+  int next_slot = 0;                  // (slot 0) the slot of the next frame
+  adr_workspace* last_slot = nullptr;  // (slot 0) the slot of the last frame
 };
 
 namespace adr {
@@ -272,6 +286,10 @@ void workspace_release_frame_arenas(adr_workspace* ws);
 // Grows ws's arenas for a frame (nothing is enqueued); ADR_E_WORKSPACE for
 // a fixed-memory workspace that is too small.
 adr_status ensure_capacity(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles, hipStream_t stream);
+
+// Creates a workspace; pipelined: with the second frame slot and the side
+// stream of adr_workspace_create (the server's slots are not pipelined).
+adr_status workspace_create(const adr_allocator* allocator, bool pipelined, adr_workspace** out);
 
 // Thread-local error message for adr_last_error.
 void set_error(const std::string& msg);

@@ -228,6 +228,7 @@ void workspace_release_frame_arenas(adr_workspace* ws) {
 using namespace adr;
 
 static void free_workspace(adr_workspace* ws) {
+  if (ws->twin) free_workspace(ws->twin);
   Arena* arenas[] = {&ws->gauss_arena, &ws->pair_arena, &ws->tile_arena, &ws->fixed_arena, &ws->grad_arena};
   for (Arena* a : arenas) release(ws, *a, nullptr, false);
   free_retired(ws);
@@ -235,6 +236,9 @@ static void free_workspace(adr_workspace* ws) {
   if (ws->notify_host) (void)hipHostFree(ws->notify_host);
   for (auto& e : ws->ev)
     if (e) (void)hipEventDestroy(e);
+  if (ws->prep_done) (void)hipEventDestroy(ws->prep_done);
+  if (ws->slot_free) (void)hipEventDestroy(ws->slot_free);
+  if (ws->side) (void)hipStreamDestroy(ws->side);
   delete ws;
 }
 
@@ -242,7 +246,8 @@ extern "C" const char* adr_last_error(void) { return g_error.c_str(); }
 
 extern "C" const char* adr_version(void) { return "adr-gfx950 0.2"; }
 
-extern "C" adr_status adr_workspace_create(const adr_allocator* allocator, adr_workspace** out) {
+namespace adr {
+adr_status workspace_create(const adr_allocator* allocator, bool pipelined, adr_workspace** out) {
   if (!out) {
     set_error("adr_workspace_create: NULL argument");
     return ADR_E_INVALID;
@@ -294,8 +299,31 @@ extern "C" adr_status adr_workspace_create(const adr_allocator* allocator, adr_w
       return ADR_E_HIP;
     }
   }
+  if (pipelined) {
+    adr_status st = workspace_create(allocator, false, &ws->twin);
+    if (st != ADR_OK) {
+      free_workspace(ws);
+      return st;
+    }
+    // default priority (the stream of every frame's early stages)
+    bool ok2 = hipStreamCreateWithFlags(&ws->side, hipStreamNonBlocking) == hipSuccess;
+    for (adr_workspace* s : {ws, ws->twin})
+      ok2 = ok2 && hipEventCreateWithFlags(&s->prep_done, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&s->slot_free, hipEventDisableTiming) == hipSuccess;
+    if (!ok2) {
+      (void)hipGetLastError();
+      free_workspace(ws);
+      set_error("adr_workspace_create: could not create the side stream or its events");
+      return ADR_E_HIP;
+    }
+  }
   *out = ws;
   return ADR_OK;
+}
+}  // namespace adr
+
+extern "C" adr_status adr_workspace_create(const adr_allocator* allocator, adr_workspace** out) {
+  return workspace_create(allocator, true, out);
 }
 
 extern "C" void adr_workspace_destroy(adr_workspace* ws) {
@@ -315,6 +343,7 @@ extern "C" int64_t adr_workspace_capacity_bytes(const adr_workspace* ws) {
   size_t b = ws->gauss_arena.bytes + ws->pair_arena.bytes + ws->tile_arena.bytes + ws->fixed_arena.bytes +
              ws->grad_arena.bytes;
   for (const Arena& a : ws->retired) b += a.bytes;
+  if (ws->twin) b += (size_t)adr_workspace_capacity_bytes(ws->twin);
   return (int64_t)b;
 }
 
@@ -336,7 +365,10 @@ extern "C" adr_status adr_workspace_reserve(adr_workspace* ws, int64_t n_gauss, 
   if ((st = grow_arena(ws, ws->pair_arena, ws->pair_capacity, n_pairs, carve_pair_arena, false, false, nullptr,
                        "pairs")) != ADR_OK)
     return st;
-  return grow_arena(ws, ws->tile_arena, ws->tile_capacity, n_tiles, carve_tile_arena, false, false, nullptr, "tiles");
+  if ((st = grow_arena(ws, ws->tile_arena, ws->tile_capacity, n_tiles, carve_tile_arena, false, false, nullptr,
+                       "tiles")) != ADR_OK)
+    return st;
+  return ws->twin ? adr_workspace_reserve(ws->twin, n_gauss, n_pairs, n_tiles) : ADR_OK;
 }
 
 namespace adr {
@@ -576,6 +608,7 @@ adr_status render_finish(const adr_scene* scene, const adr_camera* cam, const ad
                          bool blend_launched) {
   const DeviceScene& s = scene->d;
   const bool timing = (p->flags & ADR_FLAG_TIMING) != 0 && ws->ev[0] != nullptr;
+  if (timing) ADR_HIP(hipEventRecord(ws->ev[11], stream));
   if (!blend_launched)
     ADR_HIP(launch_render(ws->rec, ws->exact, plan.vals, ws->ranges, ws->tile_order, plan.n_pairs, s.n, plan.cam,
                           plan.blend, out, plan.want_load, ws, stream));
@@ -621,8 +654,33 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if (st != ADR_OK) return st;
   hipStream_t stream = (hipStream_t)stream_ptr;
   FramePlan plan;
-  if ((st = render_prepare(scene, cam, p, out, ws, stream, plan)) != ADR_OK) return st;
-  return render_finish(scene, cam, p, out, ws, stream, plan, false);
+  if (!ws->twin) {
+    ws->last_slot = ws;
+    if ((st = render_prepare(scene, cam, p, out, ws, stream, plan)) != ADR_OK) return st;
+    return render_finish(scene, cam, p, out, ws, stream, plan, false);
+  }
+  // Pipelined: the frame's stages up to the tile order go to the side stream
+  // when they depend on nothing the caller's stream may still be changing
+  // (an owned scene: immutable; the slot: free once its previous frame is
+  // done), so they overlap the previous frame's blend. A borrowed scene (the
+  // caller's arrays, which the caller may change between frames) runs every
+  // stage on the caller's stream.
+  adr_workspace* slot = ws->next_slot ? ws->twin : ws;
+  ws->next_slot ^= 1;
+  ws->last_slot = slot;
+  const bool overlap = !scene->d.borrowed;
+  hipStream_t early = overlap ? ws->side : stream;
+  ADR_HIP(hipStreamWaitEvent(early, slot->slot_free, 0));
+  st = render_prepare(scene, cam, p, out, slot, early, plan);
+  if (overlap) {  // the caller's stream takes over after the side stream's part (also after a failure)
+    ADR_HIP(hipEventRecord(slot->prep_done, early));
+    ADR_HIP(hipStreamWaitEvent(stream, slot->prep_done, 0));
+  }
+  if (st == ADR_OK) st = render_finish(scene, cam, p, out, slot, stream, plan, false);
+  slot->last_stream = stream;  // where the frame's last work (and its counters) are
+  // the slot is free again once everything enqueued for this frame is done
+  ADR_HIP(hipEventRecord(slot->slot_free, stream));
+  return st;
 }
 
 namespace {
@@ -654,6 +712,8 @@ extern "C" adr_status adr_render_backward_load(const adr_scene* scene, const adr
     set_error("adr_render_backward: dl_dimage, grads, and the forward frame's final_t and l_iter are required");
     return ADR_E_INVALID;
   }
+  adr_workspace* const handle = ws;
+  if (ws->last_slot) ws = ws->last_slot;  // the frame slot of the last adr_render
   if (ws->last_scene != scene || ws->last_scene_uid != scene->uid || !same_camera(ws->last_cam, *cam) ||
       !same_params(ws->last_params, *p) || !ws->last_vals) {
     set_error("adr_render_backward: the last adr_render on this workspace was not this scene, camera and params");
@@ -671,6 +731,7 @@ extern "C" adr_status adr_render_backward_load(const adr_scene* scene, const adr
   ADR_HIP(launch_render_backward(ws->rec, ws->exact, ws->last_vals, ws->ranges, ws->last_pairs, s.n, ca, bl,
                                  fwd->final_t, fwd->l_iter, dl_dimage, dl_dload, ws->grad2d, stream));
   ADR_HIP(launch_preprocess_backward(s, ca, p->lowpass, ws->grad2d, *grads, stream));
+  if (handle->twin) ADR_HIP(hipEventRecord(ws->slot_free, stream));  // the slot's next frame waits for this
   return ADR_OK;
 }
 
@@ -681,15 +742,19 @@ extern "C" adr_status adr_render_backward(const adr_scene* scene, const adr_came
 }
 
 extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n) {
+  if (ws && ws->last_slot) ws = ws->last_slot;
   if (!ws || !ms || n <= 0 || !ws->timing_valid) return 0;
-  if (hipEventSynchronize(ws->ev[adr_workspace::kEvents - 1]) != hipSuccess) {
+  if (hipEventSynchronize(ws->ev[10]) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   int32_t k = 0;
-  for (; k < adr_workspace::kEvents - 1 && k < n; ++k) {
+  for (; k < 10 && k < n; ++k) {
     float t = 0.f;
-    if (hipEventElapsedTime(&t, ws->ev[k], ws->ev[k + 1]) != hipSuccess) {
+    // the blend from its own start: in a pipelined workspace it may wait for
+    // the previous frame's blend after the tile order is ready
+    const hipEvent_t from = k == 8 ? ws->ev[11] : ws->ev[k];
+    if (hipEventElapsedTime(&t, from, ws->ev[k + 1]) != hipSuccess) {
       (void)hipGetLastError();
       t = -1.f;
     }
@@ -699,6 +764,7 @@ extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32
 }
 
 extern "C" int32_t adr_workspace_counters(adr_workspace* ws, int64_t* out, int32_t n) {
+  if (ws && ws->last_slot) ws = ws->last_slot;
   if (!ws || !out || n <= 0 || !ws->dev_counters) return 0;
   if (hipStreamSynchronize(ws->last_stream) != hipSuccess ||
       hipMemcpy(ws->host_counters, ws->dev_counters, kCounterSlots * sizeof(unsigned long long),

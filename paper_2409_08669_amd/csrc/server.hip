@@ -448,7 +448,7 @@ extern "C" adr_status adr_server_create(const adr_server_config* config, adr_ser
         hipEventCreateWithFlags(&s->prepared, hipEventDisableTiming) != hipSuccess) {
       st = ADR_E_HIP;
     } else {
-      st = adr_workspace_create(&sv->pool_alloc, &s->ws);
+      st = workspace_create(&sv->pool_alloc, false, &s->ws);
       if (st == ADR_OK) s->ws->headroom = false;  // arenas sized to the frame: the pool keeps them
     }
     sv->slots.push_back(std::move(s));

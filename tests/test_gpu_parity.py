@@ -187,7 +187,8 @@ def test_reserved_workspace_allocates_nothing_while_rendering(P, small):
     r = P.Workspace()
     r.reserve(s.n, o["n_pairs"], tiles)
     before = r.capacity_bytes
-    assert before == P.Workspace.bytes_for(s.n, o["n_pairs"], tiles)
+    # two frame slots, each sized for the frame
+    assert before == 2 * P.Workspace.bytes_for(s.n, o["n_pairs"], tiles)
     for mode in (0, 1, 2):
         gpu_frame(P, r, sg, cam, mode, debug=False)
     assert r.capacity_bytes == before
@@ -292,6 +293,51 @@ def test_sh_degree3_scene_parity(P, ws):
     o = O.render_frame(s, cam, oracle_params(2))
     check_integer_stage(g, o, s.n)
     check_pixels(g, o)
+
+
+def test_pipelined_frames_match_single_frames(P):
+    """Consecutive adr_render calls on one workspace alternate its two frame
+    slots, and a frame's stages up to the tile order run on the workspace's
+    side stream, overlapping the previous frame's blend. Eight frames of
+    three different scenes and image sizes (so that the slots' arenas grow
+    between frames) are enqueued back to back, each into its own outputs,
+    with no synchronisation; each must equal, bit for bit, the same frame
+    rendered alone on a fresh workspace. The last two also run with the
+    timing flag."""
+    import torch
+    cfgs = [(scene_clusters(40_000, seed=3), camera_orbit(30.0, 20.0, 45.0, 320, 240), 2),
+            (scene_small(2000, seed=0), camera_small(), 0),
+            (scene_clusters(200_000, seed=6), camera_orbit(30.0, 25.0, 120.0, 640, 480), 1)]
+    gpu_scenes = [P.Scene.from_synth(c[0]) for c in cfgs]
+
+    def outputs(cam):
+        h, w = cam.height, cam.width
+        return dict(image=torch.empty((3, h, w), device="cuda"), final_t=torch.empty((h, w), device="cuda"),
+                    l_iter=torch.empty((h, w), dtype=torch.int32, device="cuda"),
+                    l_blend=torch.empty((h, w), dtype=torch.int32, device="cuda"),
+                    load_sums=torch.zeros(4, dtype=torch.int64, device="cuda"))
+
+    seq = [0, 1, 2, 0, 2, 1, 0, 2]
+    ws = P.Workspace()
+    got = []
+    for i, k in enumerate(seq):
+        _, cam, mode = cfgs[k]
+        out = outputs(cam)
+        flags = P.ADR_FLAG_TIMING if i >= 6 else 0
+        P.render(gpu_scenes[k], cam, P.RenderParams(cull=mode, flags=flags), ws, **out)
+        got.append(out)
+    torch.cuda.synchronize()
+    for i, k in enumerate(seq):
+        _, cam, mode = cfgs[k]
+        ref = outputs(cam)
+        fresh = P.Workspace()
+        P.render(gpu_scenes[k], cam, P.RenderParams(cull=mode), fresh, **ref)
+        torch.cuda.synchronize()
+        for name in ref:
+            assert torch.equal(got[i][name], ref[name]), (i, k, name)
+        fresh.close()
+    say(f"pipelined: {len(seq)} frames bitwise equal to single frames")
+    ws.close()
 
 
 def test_load_balancing_cap_parity(P, ws, small):
