@@ -192,15 +192,16 @@ int64_t adr_scene_size(const adr_scene* scene);
 /* Device bytes the scene holds (0 for a borrowed scene). */
 int64_t adr_scene_bytes(const adr_scene* scene);
 
-/* Creates an empty workspace on the current device. It holds two frame
- * slots that consecutive adr_render calls alternate between, and a side
+/* Creates an empty workspace on the current device. It holds three frame
+ * slots that consecutive adr_render calls take in turn, each with a side
  * stream (default priority): for a scene that is not borrowed, a frame's
- * stages up to the tile order run on the side stream, which waits only for
- * the previous frame of the same slot (its blend, copies and any backward),
- * not for the caller's stream, so they overlap the previous frame's blend;
- * the blend and everything after it run on the caller's stream after the
- * side stream's part. Outputs are only written on the caller's stream, and
- * an owned scene is immutable, so every frame's results are as if all of it
+ * stages up to the tile order run on its slot's side stream, which waits
+ * only for the previous frame of the same slot (three frames earlier: its
+ * blend, copies and any backward), not for the caller's stream, so they
+ * overlap the early stages and the blend of the frames before it; the blend
+ * and everything after it run on the caller's stream after the side
+ * stream's part. Outputs are only written on the caller's stream, and an
+ * owned scene is immutable, so every frame's results are as if all of it
  * ran on the caller's stream. A borrowed scene runs every stage on the
  * caller's stream (the caller may change its arrays between frames).
  * allocator (may be NULL)
@@ -215,16 +216,16 @@ int64_t adr_scene_bytes(const adr_scene* scene);
 adr_status adr_workspace_create(const adr_allocator* allocator, adr_workspace** out);
 /* Waits for the device, then releases every arena. */
 void adr_workspace_destroy(adr_workspace* ws);
-/* Grows the arenas of both frame slots (never shrinks them) to hold a
+/* Grows the arenas of every frame slot (never shrinks them) to hold a
  * frame of n_gauss Gaussians, n_pairs Gaussian-tile pairs and n_tiles tiles,
  * and frees the arenas kept from earlier growth. Synchronises the device. A
  * render that stays within the reserved sizes allocates nothing. */
 adr_status adr_workspace_reserve(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles);
 /* Device bytes one frame slot needs for such a frame (arena sizes, without
  * growth headroom); -1 for negative arguments. Host arithmetic only. A
- * workspace reserved for the frame holds twice this (two slots). */
+ * workspace reserved for the frame holds three times this (three slots). */
 int64_t adr_workspace_bytes(int64_t n_gauss, int64_t n_pairs, int64_t n_tiles);
-/* Device bytes the arenas of both slots hold now, kept arenas included. */
+/* Device bytes the arenas of all slots hold now, kept arenas included. */
 int64_t adr_workspace_capacity_bytes(const adr_workspace* ws);
 
 /* Renders one frame: Preprocess (projection, SH colour, cull per params.cull),

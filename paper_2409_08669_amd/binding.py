@@ -342,7 +342,7 @@ class Workspace:
 
     @staticmethod
     def bytes_for(n_gauss: int, n_pairs: int, n_tiles: int) -> int:
-        """adr_workspace_bytes: device bytes one frame slot needs (a workspace holds two)."""
+        """adr_workspace_bytes: device bytes one frame slot needs (a workspace holds three)."""
         return int(load().adr_workspace_bytes(int(n_gauss), int(n_pairs), int(n_tiles)))
 
     def counters(self) -> dict:

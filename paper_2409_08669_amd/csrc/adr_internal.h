@@ -166,6 +166,11 @@ struct adr_scene {
   adr_allocator alloc{};  // provider of the owned copy (alloc == NULL: hipMalloc)
 };
 
+#ifndef ADR_FRAME_SLOTS
+#define ADR_FRAME_SLOTS 3
+#endif
+static_assert(ADR_FRAME_SLOTS >= 2, "a pipelined workspace needs at least two frame slots");
+
 struct adr_workspace {
   adr::Growth growth = adr::Growth::kDefault;
   bool headroom = true;  // grow arenas 25% past the frame's need
@@ -224,13 +229,15 @@ struct adr_workspace {
   adr_camera last_cam{};
   adr_render_params last_params{};
   const uint32_t* last_vals = nullptr;  // its sorted Gaussian ids
-  // A pipelined workspace (adr_workspace_create) has two frame slots: this
-  // handle (slot 0), which owns slot 1 (twin) and the side stream, and the
-  // twin. A frame of an owned scene runs its stages up to the tile order on
-  // the side stream, which waits only for the previous frame of the same
-  // slot, so they overlap the blend of the frame before on the caller's
-  // stream. Both slots have their own arenas, events and pinned words.
-  adr_workspace* twin = nullptr;
+  // A pipelined workspace (adr_workspace_create) has kFrameSlots frame slots
+  // that consecutive frames take in turn: this handle (slot 0), which owns
+  // the others, and slots 1.. . A frame of an owned scene runs its stages up
+  // to the tile order on its slot's side stream, which waits only for the
+  // previous frame of the same slot, so they overlap the early stages and
+  // the blend of the frames before it. Every slot has its own arenas, side
+  // stream, events and pinned words.
+  static constexpr int kFrameSlots = ADR_FRAME_SLOTS;
+  adr_workspace* slots[kFrameSlots] = {};  // (slot 0) every slot, slots[0] == this; null when not pipelined
   hipStream_t side = nullptr;
   hipEvent_t prep_done = nullptr;     // the slot's stages up to the tile order (side stream)
   hipEvent_t slot_free = nullptr;     // the slot's last frame or backward (caller's stream)
@@ -287,8 +294,8 @@ void workspace_release_frame_arenas(adr_workspace* ws);
 // a fixed-memory workspace that is too small.
 adr_status ensure_capacity(adr_workspace* ws, int64_t n_gauss, int64_t n_pairs, int64_t n_tiles, hipStream_t stream);
 
-// Creates a workspace; pipelined: with the second frame slot and the side
-// stream of adr_workspace_create (the server's slots are not pipelined).
+// Creates a workspace; pipelined: with the frame slots and side streams of
+// adr_workspace_create (the server's slots are not pipelined).
 adr_status workspace_create(const adr_allocator* allocator, bool pipelined, adr_workspace** out);
 
 // Thread-local error message for adr_last_error.
@@ -337,8 +344,8 @@ hipError_t launch_tile_ranges(const uint32_t* tiles, int64_t n_pairs, uint32_t* 
 hipError_t launch_compose_keys(const uint32_t* tiles, const uint32_t* vals, const RenderRecord* rec,
                                int64_t n_pairs, int64_t n_gauss, uint64_t* keys, hipStream_t stream);
 int64_t tile_order_scratch(int n_tiles);
-hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order, uint32_t* counts,
-                             hipStream_t stream);
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int tiles_x, int tiles_y, uint32_t* order,
+                             uint32_t* counts, hipStream_t stream);
 hipError_t launch_render(const RenderRecord* rec, const ExactRecord* exact, const uint32_t* vals,
                          const uint32_t* ranges, const uint32_t* order, int64_t n_pairs, int64_t n_gauss,
                          const CamArgs& cam, const BlendArgs& blend, const adr_frame* out, bool want_load,

@@ -228,7 +228,9 @@ void workspace_release_frame_arenas(adr_workspace* ws) {
 using namespace adr;
 
 static void free_workspace(adr_workspace* ws) {
-  if (ws->twin) free_workspace(ws->twin);
+  if (ws->slots[0] == ws)
+    for (int i = 1; i < adr_workspace::kFrameSlots; ++i)
+      if (ws->slots[i]) free_workspace(ws->slots[i]);
   Arena* arenas[] = {&ws->gauss_arena, &ws->pair_arena, &ws->tile_arena, &ws->fixed_arena, &ws->grad_arena};
   for (Arena* a : arenas) release(ws, *a, nullptr, false);
   free_retired(ws);
@@ -300,20 +302,23 @@ adr_status workspace_create(const adr_allocator* allocator, bool pipelined, adr_
     }
   }
   if (pipelined) {
-    adr_status st = workspace_create(allocator, false, &ws->twin);
-    if (st != ADR_OK) {
-      free_workspace(ws);
-      return st;
+    ws->slots[0] = ws;
+    for (int i = 1; i < adr_workspace::kFrameSlots; ++i) {
+      adr_status st = workspace_create(allocator, false, &ws->slots[i]);
+      if (st != ADR_OK) {
+        free_workspace(ws);
+        return st;
+      }
     }
-    // default priority (the stream of every frame's early stages)
-    bool ok2 = hipStreamCreateWithFlags(&ws->side, hipStreamNonBlocking) == hipSuccess;
-    for (adr_workspace* s : {ws, ws->twin})
-      ok2 = ok2 && hipEventCreateWithFlags(&s->prep_done, hipEventDisableTiming) == hipSuccess &&
+    bool ok2 = true;
+    for (adr_workspace* s : ws->slots)  // default priority: every slot's early stages
+      ok2 = ok2 && hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&s->prep_done, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&s->slot_free, hipEventDisableTiming) == hipSuccess;
     if (!ok2) {
       (void)hipGetLastError();
       free_workspace(ws);
-      set_error("adr_workspace_create: could not create the side stream or its events");
+      set_error("adr_workspace_create: could not create the side streams or their events");
       return ADR_E_HIP;
     }
   }
@@ -343,7 +348,8 @@ extern "C" int64_t adr_workspace_capacity_bytes(const adr_workspace* ws) {
   size_t b = ws->gauss_arena.bytes + ws->pair_arena.bytes + ws->tile_arena.bytes + ws->fixed_arena.bytes +
              ws->grad_arena.bytes;
   for (const Arena& a : ws->retired) b += a.bytes;
-  if (ws->twin) b += (size_t)adr_workspace_capacity_bytes(ws->twin);
+  if (ws->slots[0] == ws)
+    for (int i = 1; i < adr_workspace::kFrameSlots; ++i) b += (size_t)adr_workspace_capacity_bytes(ws->slots[i]);
   return (int64_t)b;
 }
 
@@ -368,7 +374,10 @@ extern "C" adr_status adr_workspace_reserve(adr_workspace* ws, int64_t n_gauss, 
   if ((st = grow_arena(ws, ws->tile_arena, ws->tile_capacity, n_tiles, carve_tile_arena, false, false, nullptr,
                        "tiles")) != ADR_OK)
     return st;
-  return ws->twin ? adr_workspace_reserve(ws->twin, n_gauss, n_pairs, n_tiles) : ADR_OK;
+  if (ws->slots[0] == ws)
+    for (int i = 1; i < adr_workspace::kFrameSlots; ++i)
+      if ((st = adr_workspace_reserve(ws->slots[i], n_gauss, n_pairs, n_tiles)) != ADR_OK) return st;
+  return ADR_OK;
 }
 
 namespace adr {
@@ -598,7 +607,8 @@ adr_status render_prepare(const adr_scene* scene, const adr_camera* cam, const a
   ADR_HIP(launch_tile_ranges(plan.tiles, n_pairs, ws->ranges, (int32_t)n_tiles, stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[7], stream));
   // Stage 6, first part: the tiles' render order
-  ADR_HIP(launch_tile_order(ws->ranges, n_pairs, (int)n_tiles, ws->tile_order, ws->order_counts, stream));
+  ADR_HIP(launch_tile_order(ws->ranges, n_pairs, plan.cam.tiles_x, plan.cam.tiles_y, ws->tile_order, ws->order_counts,
+                            stream));
   if (timing) ADR_HIP(hipEventRecord(ws->ev[8], stream));
   return ADR_OK;
 }
@@ -654,7 +664,7 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   if (st != ADR_OK) return st;
   hipStream_t stream = (hipStream_t)stream_ptr;
   FramePlan plan;
-  if (!ws->twin) {
+  if (ws->slots[0] != ws) {
     ws->last_slot = ws;
     if ((st = render_prepare(scene, cam, p, out, ws, stream, plan)) != ADR_OK) return st;
     return render_finish(scene, cam, p, out, ws, stream, plan, false);
@@ -665,11 +675,11 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
   // done), so they overlap the previous frame's blend. A borrowed scene (the
   // caller's arrays, which the caller may change between frames) runs every
   // stage on the caller's stream.
-  adr_workspace* slot = ws->next_slot ? ws->twin : ws;
-  ws->next_slot ^= 1;
+  adr_workspace* slot = ws->slots[ws->next_slot];
+  ws->next_slot = (ws->next_slot + 1) % adr_workspace::kFrameSlots;
   ws->last_slot = slot;
   const bool overlap = !scene->d.borrowed;
-  hipStream_t early = overlap ? ws->side : stream;
+  hipStream_t early = overlap ? slot->side : stream;
   ADR_HIP(hipStreamWaitEvent(early, slot->slot_free, 0));
   st = render_prepare(scene, cam, p, out, slot, early, plan);
   if (overlap) {  // the caller's stream takes over after the side stream's part (also after a failure)
@@ -731,7 +741,7 @@ extern "C" adr_status adr_render_backward_load(const adr_scene* scene, const adr
   ADR_HIP(launch_render_backward(ws->rec, ws->exact, ws->last_vals, ws->ranges, ws->last_pairs, s.n, ca, bl,
                                  fwd->final_t, fwd->l_iter, dl_dimage, dl_dload, ws->grad2d, stream));
   ADR_HIP(launch_preprocess_backward(s, ca, p->lowpass, ws->grad2d, *grads, stream));
-  if (handle->twin) ADR_HIP(hipEventRecord(ws->slot_free, stream));  // the slot's next frame waits for this
+  if (handle->slots[0] == handle) ADR_HIP(hipEventRecord(ws->slot_free, stream));  // the slot's next frame waits for this
   return ADR_OK;
 }
 

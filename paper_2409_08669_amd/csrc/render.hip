@@ -241,22 +241,58 @@ __device__ __forceinline__ uint64_t same_bucket(int b, bool valid) {
   return m;
 }
 
-// Counting sort of the tiles by bucket in two launches over blocks of 256
-// tiles: per-block bucket counts, then each block finds its buckets' bases
-// (all blocks' counts are a few hundred words) and scatters its tiles. Each
-// wave groups its tiles by bucket with ballots, so LDS atomics are per bucket
-// per wave rather than per tile.
+// Counting sort of the tiles by bucket in two launches, one workgroup per
+// superblock of 16 x 16 tiles: per-block bucket counts, then each block finds
+// its buckets' bases (all blocks' counts are a few thousand words at most)
+// and scatters its tiles. Each wave groups its tiles by bucket with ballots,
+// so LDS atomics are per bucket per wave rather than per tile.
+//
+// Inside a bucket the tiles are ranked in scan order (superblocks row by
+// row, each row-major inside) and the ranks are dealt to the XCDs in
+// contiguous runs: the render's workgroup at position p runs on XCD p mod 8,
+// so the k-th eighth of every bucket's ranks takes the bucket's positions
+// with p mod 8 = k. Tiles that run on one XCD at the same time are then
+// neighbours, which share most of their Gaussians, and the records those
+// tiles read are fetched into that XCD's L2 once rather than once per XCD.
 constexpr int kOrderBlock = 256;
+constexpr int kOrderSuper = 16;  // superblock side in tiles (kOrderSuper^2 = kOrderBlock)
+constexpr int kXcds = 8;
 
-__global__ void __launch_bounds__(kOrderBlock) order_count_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
-                                                                  uint32_t n_pairs, uint32_t* __restrict__ counts) {
+// This lane's tile of the superblock blockIdx.x, or valid = false past the grid.
+__device__ __forceinline__ int superblock_tile(int tiles_x, int tiles_y, bool& valid) {
+  const int n_sbx = (tiles_x + kOrderSuper - 1) / kOrderSuper;
+  const int tx = ((int)blockIdx.x % n_sbx) * kOrderSuper + ((int)threadIdx.x % kOrderSuper);
+  const int ty = ((int)blockIdx.x / n_sbx) * kOrderSuper + ((int)threadIdx.x / kOrderSuper);
+  valid = tx < tiles_x && ty < tiles_y;
+  return valid ? ty * tiles_x + tx : 0;
+}
+
+// Position of rank r among the n tiles of the bucket whose positions start
+// at b0: residue k = 0, 1, ... takes the next run of ranks, placed at the
+// bucket's positions p with p mod 8 = k in increasing order (a bijection of
+// [0, n) onto [b0, b0 + n)).
+__device__ __forceinline__ uint32_t xcd_position(uint32_t b0, uint32_t n, uint32_t r) {
+  uint32_t start = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < (uint32_t)kXcds; ++k) {
+    const uint32_t first = b0 + (k + kXcds - b0 % kXcds) % kXcds;
+    const uint32_t cnt = first < b0 + n ? (b0 + n - first + kXcds - 1) / kXcds : 0u;
+    if (r < start + cnt) return first + kXcds * (r - start);
+    start += cnt;
+  }
+  return b0 + r;  // not reached for r < n
+}
+
+__global__ void __launch_bounds__(kOrderBlock) order_count_kernel(const uint32_t* __restrict__ ranges, int tiles_x,
+                                                                  int tiles_y, uint32_t n_pairs,
+                                                                  uint32_t* __restrict__ counts) {
   __shared__ uint32_t cnt[kOrderBuckets];
   const int lane = threadIdx.x & 63;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0u;
   __syncthreads();
-  const int t = blockIdx.x * kOrderBlock + threadIdx.x;
-  const bool valid = t < n_tiles;
+  bool valid;
+  const int t = superblock_tile(tiles_x, tiles_y, valid);
   const int b = valid ? order_bucket(ranges, t, n_pairs) : 0;
   const uint64_t m = same_bucket(b, valid);
   if (valid && (m & lt) == 0) atomicAdd(&cnt[b], (uint32_t)__popcll(m));
@@ -264,46 +300,48 @@ __global__ void __launch_bounds__(kOrderBlock) order_count_kernel(const uint32_t
   if (threadIdx.x < kOrderBuckets) counts[threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
 
-__global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
-                                                                    uint32_t n_pairs,
+__global__ void __launch_bounds__(kOrderBlock) order_scatter_kernel(const uint32_t* __restrict__ ranges, int tiles_x,
+                                                                    int tiles_y, uint32_t n_pairs,
                                                                     const uint32_t* __restrict__ counts,
                                                                     uint32_t* __restrict__ order) {
-  __shared__ uint32_t base[kOrderBuckets];
+  __shared__ uint32_t base[kOrderBuckets];    // first position of the bucket
+  __shared__ uint32_t total[kOrderBuckets];   // tiles in the bucket
+  __shared__ uint32_t before[kOrderBuckets];  // the bucket's tiles in earlier blocks
   __shared__ uint32_t wave_cnt[kOrderBlock / 64][kOrderBuckets];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int nb = gridDim.x;
+  const uint32_t n_tiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
   if (threadIdx.x < kOrderBuckets) {
-    uint32_t total = 0, before = 0;
+    uint32_t tot = 0, bef = 0;
     for (int k = 0; k < nb; ++k) {
       const uint32_t c = counts[threadIdx.x * nb + k];
-      total += c;
-      before += k < (int)blockIdx.x ? c : 0u;
+      tot += c;
+      bef += k < (int)blockIdx.x ? c : 0u;
     }
-    base[threadIdx.x] = before;
-    wave_cnt[0][threadIdx.x] = total;  // bucket totals, scanned below
+    before[threadIdx.x] = bef;
+    total[threadIdx.x] = tot;
   }
+  for (int i = threadIdx.x; i < (kOrderBlock / 64) * kOrderBuckets; i += kOrderBlock) (&wave_cnt[0][0])[i] = 0u;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
     for (int k = 0; k < kOrderBuckets; ++k) {
-      base[k] += run;
-      run += wave_cnt[0][k];
+      base[k] = run;
+      run += total[k];
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < (kOrderBlock / 64) * kOrderBuckets; i += kOrderBlock) (&wave_cnt[0][0])[i] = 0u;
-  __syncthreads();
-  const int t = blockIdx.x * kOrderBlock + threadIdx.x;
-  const bool valid = t < n_tiles;
+  bool valid;
+  const int t = superblock_tile(tiles_x, tiles_y, valid);
   const int b = valid ? order_bucket(ranges, t, n_pairs) : 0;
   const uint64_t m = same_bucket(b, valid);
   if (valid && (m & lt) == 0) wave_cnt[wid][b] = (uint32_t)__popcll(m);
   __syncthreads();
   if (valid) {
-    uint32_t pos = base[b] + (uint32_t)__popcll(m & lt);
-    for (int w = 0; w < wid; ++w) pos += wave_cnt[w][b];
-    if (pos < (uint32_t)n_tiles) order[pos] = (uint32_t)t;
+    uint32_t r = before[b] + (uint32_t)__popcll(m & lt);
+    for (int w = 0; w < wid; ++w) r += wave_cnt[w][b];
+    const uint32_t pos = xcd_position(base[b], total[b], r);
+    if (pos < n_tiles) order[pos] = (uint32_t)t;
   }
 }
 
@@ -953,15 +991,21 @@ __global__ void __launch_bounds__(256) render_backward_kernel(
 
 }  // namespace
 
-int64_t tile_order_scratch(int n_tiles) { return (int64_t)kOrderBuckets * ((n_tiles + kOrderBlock - 1) / kOrderBlock); }
+// Superblocks of a tiles_x x tiles_y grid of n tiles: at most
+// (tx/16 + 1)(ty/16 + 1) = n/256 + (tx + ty)/16 + 1 <= n/256 + n/16 + 2.
+static int64_t order_blocks_bound(int64_t n_tiles) { return n_tiles / 256 + n_tiles / 16 + 2; }
 
-// counts: tile_order_scratch(n_tiles) words
-hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int n_tiles, uint32_t* order, uint32_t* counts,
-                             hipStream_t stream) {
-  if (n_tiles <= 0) return hipSuccess;
-  const int nb = (n_tiles + kOrderBlock - 1) / kOrderBlock;
-  order_count_kernel<<<nb, kOrderBlock, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, counts);
-  order_scatter_kernel<<<nb, kOrderBlock, 0, stream>>>(ranges, n_tiles, (uint32_t)n_pairs, counts, order);
+int64_t tile_order_scratch(int n_tiles) { return (int64_t)kOrderBuckets * order_blocks_bound(n_tiles); }
+
+// counts: tile_order_scratch(tiles_x * tiles_y) words
+hipError_t launch_tile_order(const uint32_t* ranges, int64_t n_pairs, int tiles_x, int tiles_y, uint32_t* order,
+                             uint32_t* counts, hipStream_t stream) {
+  if (tiles_x <= 0 || tiles_y <= 0) return hipSuccess;
+  const int64_t nb = (int64_t)((tiles_x + kOrderSuper - 1) / kOrderSuper) * ((tiles_y + kOrderSuper - 1) / kOrderSuper);
+  if (nb > order_blocks_bound((int64_t)tiles_x * tiles_y)) return hipErrorInvalidValue;
+  order_count_kernel<<<(unsigned)nb, kOrderBlock, 0, stream>>>(ranges, tiles_x, tiles_y, (uint32_t)n_pairs, counts);
+  order_scatter_kernel<<<(unsigned)nb, kOrderBlock, 0, stream>>>(ranges, tiles_x, tiles_y, (uint32_t)n_pairs, counts,
+                                                                  order);
   return hipGetLastError();
 }
 

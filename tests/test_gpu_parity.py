@@ -187,8 +187,8 @@ def test_reserved_workspace_allocates_nothing_while_rendering(P, small):
     r = P.Workspace()
     r.reserve(s.n, o["n_pairs"], tiles)
     before = r.capacity_bytes
-    # two frame slots, each sized for the frame
-    assert before == 2 * P.Workspace.bytes_for(s.n, o["n_pairs"], tiles)
+    # three frame slots, each sized for the frame
+    assert before == 3 * P.Workspace.bytes_for(s.n, o["n_pairs"], tiles)
     for mode in (0, 1, 2):
         gpu_frame(P, r, sg, cam, mode, debug=False)
     assert r.capacity_bytes == before
@@ -296,14 +296,14 @@ def test_sh_degree3_scene_parity(P, ws):
 
 
 def test_pipelined_frames_match_single_frames(P):
-    """Consecutive adr_render calls on one workspace alternate its two frame
-    slots, and a frame's stages up to the tile order run on the workspace's
-    side stream, overlapping the previous frame's blend. Eight frames of
-    three different scenes and image sizes (so that the slots' arenas grow
-    between frames) are enqueued back to back, each into its own outputs,
-    with no synchronisation; each must equal, bit for bit, the same frame
-    rendered alone on a fresh workspace. The last two also run with the
-    timing flag."""
+    """Consecutive adr_render calls on one workspace take its three frame
+    slots in turn, and a frame's stages up to the tile order run on its
+    slot's side stream, overlapping the early stages and the blend of the
+    frames before it. Ten frames of three different scenes and image sizes,
+    ordered so that every slot renders all three (its arenas grow between
+    frames), are enqueued back to back, each into its own outputs, with no
+    synchronisation; each must equal, bit for bit, the same frame rendered
+    alone on a fresh workspace. The last two also run with the timing flag."""
     import torch
     cfgs = [(scene_clusters(40_000, seed=3), camera_orbit(30.0, 20.0, 45.0, 320, 240), 2),
             (scene_small(2000, seed=0), camera_small(), 0),
@@ -317,13 +317,13 @@ def test_pipelined_frames_match_single_frames(P):
                     l_blend=torch.empty((h, w), dtype=torch.int32, device="cuda"),
                     load_sums=torch.zeros(4, dtype=torch.int64, device="cuda"))
 
-    seq = [0, 1, 2, 0, 2, 1, 0, 2]
+    seq = [0, 1, 2, 1, 2, 0, 2, 0, 1, 0]  # frame i in slot i mod 3
     ws = P.Workspace()
     got = []
     for i, k in enumerate(seq):
         _, cam, mode = cfgs[k]
         out = outputs(cam)
-        flags = P.ADR_FLAG_TIMING if i >= 6 else 0
+        flags = P.ADR_FLAG_TIMING if i >= len(seq) - 2 else 0
         P.render(gpu_scenes[k], cam, P.RenderParams(cull=mode, flags=flags), ws, **out)
         got.append(out)
     torch.cuda.synchronize()
