@@ -58,7 +58,8 @@ def parse():
     ap.add_argument("--no-lb", action="store_true",
                     help="skip the load-balancing sweep on the 3M-Gaussian load-imbalanced workload")
     ap.add_argument("--train-iters", type=int, default=600, help="iterations per run of --only train")
-    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb", "seeds"],
+    ap.add_argument("--only", choices=["3sigma", "adaptive", "aabb", "aabb_pairs_only", "backward", "train", "lb", "seeds",
+                                       "serve"],
                     default=None,
                     help="time one mode only (for profiler runs)")
     ap.add_argument("--no-alpha-sweep", action="store_true",
@@ -140,6 +141,13 @@ def measured_traffic(kernel):
 
 def main():
     args = parse()
+    if args.only == "serve":
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        import paper_2409_08669_amd as P
+        P.load()
+        print(json.dumps({"mode": "serve", "serving": serve_benchmark(P, args)}), flush=True)
+        return
     if args.only == "seeds":
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
