@@ -432,11 +432,11 @@ def main():
 
 
 def two_in_flight(P, sg, cam, params, steps, warmup, like):
-    """Frames/s with two frames in flight: consecutive frames alternate
-    between two workspaces on two streams (default priority), so that one
-    frame's Preprocess, sorts and emission overlap the previous frame's blend.
-    Every frame is still whole; only their overlap differs from the
-    back-to-back figure."""
+    """Frames/s with consecutive frames alternating between two workspaces on
+    two streams (default priority) and two sets of outputs, so that the blends
+    of consecutive frames may overlap too (on one workspace and one set of
+    outputs they are ordered on the caller's stream). Every frame is still
+    whole; only their overlap differs from the back-to-back figure."""
     import torch
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     spaces = [P.Workspace(), P.Workspace()]

@@ -669,10 +669,11 @@ extern "C" adr_status adr_render(const adr_scene* scene, const adr_camera* cam, 
     if ((st = render_prepare(scene, cam, p, out, ws, stream, plan)) != ADR_OK) return st;
     return render_finish(scene, cam, p, out, ws, stream, plan, false);
   }
-  // Pipelined: the frame's stages up to the tile order go to the side stream
-  // when they depend on nothing the caller's stream may still be changing
-  // (an owned scene: immutable; the slot: free once its previous frame is
-  // done), so they overlap the previous frame's blend. A borrowed scene (the
+  // Pipelined: the frame takes the next slot, and its stages up to the tile
+  // order go to that slot's side stream when they depend on nothing the
+  // caller's stream may still be changing (an owned scene: immutable; the
+  // slot: free once its previous frame is done), so they overlap the early
+  // stages and the blends of the frames before it. A borrowed scene (the
   // caller's arrays, which the caller may change between frames) runs every
   // stage on the caller's stream.
   adr_workspace* slot = ws->slots[ws->next_slot];
@@ -762,7 +763,7 @@ extern "C" int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32
   for (; k < 10 && k < n; ++k) {
     float t = 0.f;
     // the blend from its own start: in a pipelined workspace it may wait for
-    // the previous frame's blend after the tile order is ready
+    // the blend of the frame before after its tile order is ready
     const hipEvent_t from = k == 8 ? ws->ev[11] : ws->ev[k];
     if (hipEventElapsedTime(&t, from, ws->ev[k + 1]) != hipSuccess) {
       (void)hipGetLastError();
