@@ -59,10 +59,12 @@ typedef enum {
  * memory, immutable after creation; may be shared by concurrent renders. */
 typedef struct adr_scene adr_scene;
 
-/* Opaque per-stream scratch (per-Gaussian records, pair and sort buffers,
- * tile ranges): four device arenas (per Gaussian, per pair, per tile, and a
- * few fixed counters), each one allocation. Grows on demand; one workspace
- * must not be used by two renders at the same time. */
+/* Opaque scratch (per-Gaussian records, pair and sort buffers, tile
+ * ranges): four device arenas (per Gaussian, per pair, per tile, and a few
+ * fixed counters), each one allocation, per frame slot (see
+ * adr_workspace_create). Grows on demand. Calls on one workspace must come
+ * from one host thread at a time; consecutive renders may be enqueued
+ * without waiting for the earlier ones. */
 typedef struct adr_workspace adr_workspace;
 
 /* Caller-supplied device memory (for example a caching allocator).
@@ -230,7 +232,10 @@ int64_t adr_workspace_capacity_bytes(const adr_workspace* ws);
 
 /* Renders one frame: Preprocess (projection, SH colour, cull per params.cull),
  * InclusiveSum, DuplicateWithKeys, SortPairs, IdentifyTileRanges and Render
- * (Sec. 3.2), all on the given stream. Outputs are written into out. */
+ * (Sec. 3.2), ordered on the given stream: for a scene that is not borrowed
+ * the stages before Render run on the frame slot's side stream, which the
+ * given stream then waits for (see adr_workspace_create). Outputs are
+ * written into out, on the given stream only. */
 adr_status adr_render(const adr_scene* scene, const adr_camera* cam, const adr_render_params* params,
                       adr_frame* out, adr_workspace* ws, void* stream);
 
@@ -276,9 +281,9 @@ adr_status adr_render_backward_load(const adr_scene* scene, const adr_camera* ca
  * timing); the pair count comes back by a device-to-host copy and a wait on
  * the stream. The kernels and their launch configuration are adr_render's,
  * so the outputs are bitwise the same.
- * Limits: the per-Gaussian (about 145 bytes each) and per-tile (about 141
+ * Limits: the per-Gaussian (about 133 bytes each) and per-tile (about 149
  * bytes each) arrays must fit in the array with room for pairs, else
- * ADR_E_WORKSPACE before anything is enqueued; the pairs (about 16.5 bytes
+ * ADR_E_WORKSPACE before anything is enqueued; the pairs (about 16.1 bytes
  * each with the sort scratch) take what is left, and a frame with more returns ADR_E_WORKSPACE after
  * Preprocess with out->n_pairs set (1M Gaussians at 1920 x 1080, ~2.2M
  * pairs, fit). Every call on a GPU shares that GPU's array: calls are
@@ -296,7 +301,7 @@ int64_t adr_noalloc_scratch_bytes(void);
  * Gaussians, [3] inclusive sum, [4] duplicate with keys, [5] tile sort of the
  * pairs, [6] tile ranges, [7] tile render order, [8] render (the blend kernel
  * alone, from its own start: on a pipelined workspace the stages before it
- * run on the workspace's side stream and may end before the previous frame's
+ * run on the frame slot's side stream and may end before the previous frame's
  * blend does), [9] load-sum reduction.
  * Waits for the frame to finish. Returns the number of stages written. */
 int32_t adr_workspace_stage_times(adr_workspace* ws, float* ms, int32_t n);
